@@ -1,0 +1,169 @@
+/*
+ * submat.h -- C ABI of the MI355X (gfx950) submatrix-method library.
+ *
+ * The library computes the submatrix-method approximation X ~ A^(-1/p) of a
+ * sparse symmetric positive-definite matrix A, with X restricted to A's
+ * sparsity pattern (Lass et al., arXiv:1710.10899):
+ *
+ *   Section 3.1 (Algorithm "Construction of submatrices"): for column j,
+ *     R_j = rows holding a stored entry of column j, S_j = A[R_j, R_j].
+ *   Section 3.2: the operation is applied to every S_j; here a symmetric
+ *     eigendecomposition S_j = Q diag(lambda) Q^T with f(lambda) = lambda^(-1/p).
+ *   Section 3.3 (Algorithm "Assembly of result matrix"): column j of X on
+ *     rows R_j is column R_j.indexof(j) of f(S_j).
+ *   Section 3.4: X has exactly A's pattern; its value array is the
+ *     concatenation of those columns and A's index arrays are reused.
+ *
+ * Matrix format: CSR with int32 row pointers and column indices. The pattern
+ * must be structurally symmetric, each row strictly increasing, and every
+ * diagonal entry stored. Because the pattern is symmetric, CSR row segment j
+ * equals column j, and segment j of the output value array holds column j
+ * of X (the row-based reading of Section 3 gives the same array).
+ * Each S_j is used in its symmetric part (S_j + S_j^T)/2.
+ *
+ * Pointers: every array argument is a DEVICE pointer owned by the caller
+ * (for example a torch tensor's data_ptr()), on the current HIP device.
+ * Inputs are never written. Outputs are fully overwritten, never accumulated.
+ * `stream` is a hipStream_t (NULL = the legacy default stream); all work is
+ * enqueued on it and the call returns without waiting, except that the first
+ * call for a new sparsity pattern builds a plan (pattern validation on the
+ * device, one device-to-host copy) and allocates the library's workspace.
+ *
+ * Plans are cached by (rowptr, colind, n, nnz, device). The caller must not
+ * change a pattern's contents while its plan is cached (call
+ * submat_release() after changing it). Calls that overlap in time on
+ * different streams may share a plan's workspace and must not run
+ * concurrently; serialise them or use one stream.
+ *
+ * Errors: every int-returning call returns SUBMAT_OK (0) or a negative code;
+ * submat_strerror() names it. Invalid input is reported synchronously and
+ * nothing is written. Numerical failures are asynchronous: a submatrix with
+ * an eigenvalue <= 0 (no real inverse p-th root) or whose eigensolver did not
+ * converge yields NaN in its output segment and is counted in device
+ * counters that submat_query_status() reads. The library never aborts and
+ * never prints.
+ */
+#ifndef SUBMAT_H
+#define SUBMAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* value type of vals / x_vals / grad arrays */
+#define SUBMAT_F64 0
+#define SUBMAT_F32 1
+
+/* compute precision */
+#define SUBMAT_PREC_F64 0       /* batched FP64 eigensolves */
+#define SUBMAT_PREC_F32_MIXED 1 /* batched FP32 eigensolves (FP64 Jacobi rotation
+                                   angles); a submatrix whose FP32 eigenvalues give
+                                   lambda_min <= 0 or lambda_max/lambda_min above
+                                   the kappa threshold is redone in FP64 */
+#define SUBMAT_PREC_F64_PLAIN 2 /* FP64, one column per launch, no batching and
+                                   no graph: the per-column comparison path */
+
+/* status codes */
+#define SUBMAT_OK 0
+#define SUBMAT_EINVAL -1   /* n < 1, nnz < n, p < 1, null pointer, bad dtype/precision */
+#define SUBMAT_EPATTERN -2 /* rowptr not 0..nnz non-decreasing, column index out of range,
+                              row not strictly increasing, or pattern not symmetric */
+#define SUBMAT_ENODIAG -3  /* a diagonal entry is not stored: R_j.indexof(j) is undefined
+                              (Section 3.3) */
+#define SUBMAT_ENOMEM -4   /* device allocation failed */
+#define SUBMAT_EHIP -5     /* a HIP runtime call failed */
+#define SUBMAT_ETOOBIG -6  /* a submatrix order exceeds SUBMAT_MAX_ORDER */
+#define SUBMAT_ESAVED -7   /* `saved` buffer does not belong to this pattern/dtype */
+
+/* largest supported submatrix order m_j = nnz of row j */
+#define SUBMAT_MAX_ORDER 2048
+
+/* option keys for submat_set_option / submat_get_option */
+#define SUBMAT_OPT_KAPPA_MAX 1   /* FP64-fallback threshold on lambda_max/lambda_min (1e5) */
+#define SUBMAT_OPT_USE_GRAPH 2   /* 1: capture each call sequence once in a hipGraph and
+                                    replay it (default 1); 0: direct launches */
+#define SUBMAT_OPT_SMALL_MAX 3   /* largest order on the one-wavefront Jacobi path (64) */
+#define SUBMAT_OPT_WS_BYTES 4    /* workspace budget per plan in bytes (0: automatic) */
+#define SUBMAT_OPT_ROT_BATCH 5   /* QL sweeps applied per pass over Q (8 or 16) */
+#define SUBMAT_OPT_TUNE_FILE 6   /* reserved: autotune table is read from the path in the
+                                    environment variable SUBMAT_TUNE_FILE */
+
+/*
+ * Forward: x_vals[rowptr[j] + i] = (f(S_j))[i][c_j] for every column j and
+ * i < m_j, where c_j = R_j.indexof(j), f(lambda) = lambda^(-1/p)
+ * (Sections 3.1-3.4).
+ *   rowptr  int32[n+1], colind int32[nnz]: CSR pattern (see above).
+ *   vals    nnz values of A, type `dtype`.
+ *   p       integer >= 1.
+ *   x_vals  nnz values of X (same type), fully written.
+ *   saved   NULL, or a device buffer of submat_saved_bytes() bytes; when given, the
+ *           eigenvectors and eigenvalues of every submatrix on the large-order path
+ *           are kept there so that submat_invroot_bwd() need not recompute them.
+ */
+int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
+                       void* x_vals, void* saved, void* stream);
+
+/*
+ * Adjoint (Daleckii-Krein; the paper has no gradient): for the loss
+ * L = sum_q grad_x[q] * x_vals[q], grad_a[q] = dL/d vals[q] for every stored
+ * entry q. Per column j, with S_j = Q diag(lambda) Q^T, w = grad_x segment j,
+ * a = Q^T w, b = Q[c_j, :]^T, G[k][l] = (f(lambda_k) - f(lambda_l)) /
+ * (lambda_k - lambda_l) (f'(lambda_k) when equal) and M = G o (a b^T):
+ * D_j = Q (M + M^T)/2 Q^T, and every stored pair (R_j[k], R_j[l]) at
+ * position q receives D_j[k][l]. grad_a is fully written (zeroed first).
+ *   saved   NULL (recompute), or the buffer filled by the submat_invroot_fwd() call
+ *           with the same pattern, vals, p, dtype and precision.
+ */
+int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
+                       const void* grad_x, void* grad_a, const void* saved, void* stream);
+
+/* Bytes of the optional `saved` buffer for this pattern and dtype; < 0 on error.
+   Builds (and caches) the plan if needed (synchronous). */
+int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t n,
+                           int64_t nnz, int32_t dtype, int32_t precision);
+
+/*
+ * Synchronises `stream` and reports the device counters of the last completed
+ * fwd/bwd call on the current device: submatrices with an eigenvalue <= 0,
+ * submatrices redone in FP64 by the mixed-precision path, and submatrices whose
+ * eigensolver did not converge. Any pointer may be NULL.
+ */
+int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallback,
+                        int64_t* n_unconverged);
+
+/* Options (process-wide). Unknown keys return SUBMAT_EINVAL. */
+int submat_set_option(int32_t key, double value);
+double submat_get_option(int32_t key);
+
+/* Name of a status code (static string). */
+const char* submat_strerror(int32_t code);
+
+/* Drop every cached plan, graph and workspace (synchronises the device). */
+void submat_release(void);
+
+/* ABI version: 100*major + minor. */
+int32_t submat_version(void);
+
+/*
+ * Measurement helper: runs the forward (and, when grad_x != NULL, the adjoint)
+ * with direct launches on `stream`, times each phase with HIP events recorded on
+ * that stream, and writes per-phase totals in milliseconds to phase_ms[] and the
+ * number of launches to phase_launches[] (arrays of SUBMAT_NUM_PHASES entries).
+ * Phase order: plan-reset, small-jacobi, gather, tridiagonalise, form-q1,
+ * tridiagonal-ql, apply-rotations, apply-column, adjoint, fallback.
+ */
+#define SUBMAT_NUM_PHASES 10
+int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
+                       void* x_vals, const void* grad_x, void* grad_a, void* stream,
+                       double* phase_ms, int32_t* phase_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUBMAT_H */

@@ -1,0 +1,150 @@
+"""ctypes binding of libsubmat.so: the C ABI declared in include/submat.h,
+under the same names. Argument marshalling only; every step of the
+computation runs in the library's HIP kernels.
+
+Loading fails loudly when the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsubmat.so")
+
+SUBMAT_F64 = 0
+SUBMAT_F32 = 1
+SUBMAT_PREC_F64 = 0
+SUBMAT_PREC_F32_MIXED = 1
+SUBMAT_PREC_F64_PLAIN = 2
+
+SUBMAT_OK = 0
+SUBMAT_EINVAL = -1
+SUBMAT_EPATTERN = -2
+SUBMAT_ENODIAG = -3
+SUBMAT_ENOMEM = -4
+SUBMAT_EHIP = -5
+SUBMAT_ETOOBIG = -6
+SUBMAT_ESAVED = -7
+SUBMAT_MAX_ORDER = 2048
+
+SUBMAT_OPT_KAPPA_MAX = 1
+SUBMAT_OPT_USE_GRAPH = 2
+SUBMAT_OPT_SMALL_MAX = 3
+SUBMAT_OPT_WS_BYTES = 4
+SUBMAT_OPT_ROT_BATCH = 5
+SUBMAT_OPT_TUNE_FILE = 6
+SUBMAT_NUM_PHASES = 10
+
+PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "form-q1", "tridiagonal-ql",
+          "apply-rotations", "apply-column", "adjoint", "fallback"]
+
+# exported symbol -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "submat_invroot_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P]),
+    "submat_invroot_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "submat_saved_bytes": (_I64, [_P, _P, _I32, _I64, _I32, _I32]),
+    "submat_query_status": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "submat_set_option": (ctypes.c_int, [_I32, ctypes.c_double]),
+    "submat_get_option": (ctypes.c_double, [_I32]),
+    "submat_strerror": (ctypes.c_char_p, [_I32]),
+    "submat_release": (None, []),
+    "submat_version": (_I32, []),
+    "submat_time_phases": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
+}
+
+_lib = None
+
+
+class SubmatError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Loads libsubmat.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built; run `python -m paper_1710_10899_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    if _lib is None:
+        return f"status {code}"
+    return _lib.submat_strerror(code).decode()
+
+
+def _check(code: int, where: str) -> None:
+    if code != SUBMAT_OK:
+        raise SubmatError(code, where)
+
+
+# ---- same-name wrappers over raw pointers / integers -----------------------
+
+def submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream) -> None:
+    _check(load().submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream),
+           "submat_invroot_fwd")
+
+
+def submat_invroot_bwd(rowptr, colind, vals, n, nnz, p, dtype, precision, grad_x, grad_a, saved, stream) -> None:
+    _check(load().submat_invroot_bwd(rowptr, colind, vals, n, nnz, p, dtype, precision, grad_x, grad_a, saved,
+                                     stream), "submat_invroot_bwd")
+
+
+def submat_saved_bytes(rowptr, colind, n, nnz, dtype, precision) -> int:
+    r = load().submat_saved_bytes(rowptr, colind, n, nnz, dtype, precision)
+    if r < 0:
+        raise SubmatError(int(r), "submat_saved_bytes")
+    return int(r)
+
+
+def submat_query_status(stream) -> dict:
+    a, b, c = _I64(0), _I64(0), _I64(0)
+    _check(load().submat_query_status(stream, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "submat_query_status")
+    return {"nonpositive": a.value, "fallback": b.value, "unconverged": c.value}
+
+
+def submat_set_option(key: int, value: float) -> None:
+    _check(load().submat_set_option(key, float(value)), "submat_set_option")
+
+
+def submat_get_option(key: int) -> float:
+    return float(load().submat_get_option(key))
+
+
+def submat_strerror(code: int) -> str:
+    return load().submat_strerror(code).decode()
+
+
+def submat_release() -> None:
+    load().submat_release()
+
+
+def submat_version() -> int:
+    return int(load().submat_version())
+
+
+def submat_time_phases(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, grad_x, grad_a, stream) -> dict:
+    ms = (ctypes.c_double * SUBMAT_NUM_PHASES)()
+    nl = (_I32 * SUBMAT_NUM_PHASES)()
+    _check(load().submat_time_phases(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, grad_x, grad_a,
+                                     stream, ms, nl), "submat_time_phases")
+    return {PHASES[i]: (ms[i], nl[i]) for i in range(SUBMAT_NUM_PHASES)}

@@ -1,0 +1,670 @@
+// C-ABI layer: plan cache, size buckets, chunked workspace, launch
+// sequences, hipGraph capture and replay, status counters, phase timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "../../include/submat.h"
+#include "autotune.hpp"
+#include "kernels.hpp"
+
+using namespace submat;
+
+namespace {
+
+// ------------------------------------------------------------------ options
+struct Options {
+  double kappa_max = 1e5;
+  int use_graph = 1;
+  int small_max = 64;
+  double ws_bytes = 0.0;
+  int rot_batch = 16;
+};
+Options g_opt;
+std::mutex g_mu;
+
+#define HIP_TRY(expr)                      \
+  do {                                     \
+    hipError_t _e = (expr);                \
+    if (_e != hipSuccess) return SUBMAT_EHIP; \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  int alloc(size_t count) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    n = count;
+    if (count == 0) return SUBMAT_OK;
+    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) { p = nullptr; (void)hipGetLastError(); return SUBMAT_ENOMEM; }
+    return SUBMAT_OK;
+  }
+};
+
+// --------------------------------------------------------------- device ctx
+struct DeviceCtx {
+  int device = -1;
+  int num_cus = 0;
+  DevBuf<int64_t> status;      // ST_NSLOTS slots
+  std::vector<int64_t> last_status;
+};
+std::map<int, std::unique_ptr<DeviceCtx>> g_dev;
+
+int get_ctx(DeviceCtx** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    auto ctx = std::make_unique<DeviceCtx>();
+    ctx->device = dev;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    ctx->num_cus = prop.multiProcessorCount;
+    int rc = ctx->status.alloc(ST_NSLOTS);
+    if (rc) return rc;
+    HIP_TRY(hipMemset(ctx->status.p, 0, ST_NSLOTS * sizeof(int64_t)));
+    it = g_dev.emplace(dev, std::move(ctx)).first;
+  }
+  *out = it->second.get();
+  return SUBMAT_OK;
+}
+
+// --------------------------------------------------------------------- plan
+struct Chunk {
+  int start = 0, count = 0, max_m = 0;
+  int64_t slab_bytes = 0;   // S (and Q, W) bytes for this chunk
+  int64_t vec_bytes = 0;    // per vector array
+  int64_t rot_bytes = 0;
+  int64_t sw_ints = 0;
+};
+
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t stamp = 0;
+};
+
+struct Plan {
+  int device = 0;
+  const int32_t* rowptr = nullptr;
+  const int32_t* colind = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int small_max = 64;
+  std::vector<int32_t> h_m;
+  DevBuf<int32_t> d_m, d_c;
+  // buckets (columns, largest m first)
+  std::vector<int32_t> small_items, large_items;
+  DevBuf<int32_t> d_small, d_large;
+  int small_mmax = 0, large_mmax = 0;
+  // large-item layout
+  DevBuf<int32_t> d_ldm;
+  DevBuf<int64_t> d_off, d_voff, d_roff, d_swoff, d_sqoff, d_sdoff;
+  std::vector<int64_t> h_sqoff, h_sdoff;
+  std::vector<Chunk> chunks;
+  int64_t saved_q_bytes = 0, saved_bytes = 0;
+  // workspace
+  DevBuf<char> S, Q, W, dv, ev, tv, rot;
+  DevBuf<int32_t> sweeps, nsweeps, flags;
+  DevBuf<int32_t> counters;
+  int ncounters = 0;
+  // graphs
+  std::vector<GraphEntry> graphs;
+  uint64_t stamp = 0;
+  hipStream_t cap_stream = nullptr;
+  ~Plan() {
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+using PlanKey = std::tuple<int, uintptr_t, uintptr_t, int32_t, int64_t>;
+std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, hipStream_t stream,
+               DeviceCtx* ctx, Plan** out) {
+  PlanKey key{ctx->device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second.get();
+    return SUBMAT_OK;
+  }
+  auto plan = std::make_unique<Plan>();
+  Plan& P = *plan;
+  P.device = ctx->device;
+  P.rowptr = rowptr;
+  P.colind = colind;
+  P.n = n;
+  P.nnz = nnz;
+  P.small_max = std::min(64, std::max(1, g_opt.small_max));
+  int rc;
+  if ((rc = P.d_m.alloc(n)) || (rc = P.d_c.alloc(n))) return rc;
+  DevBuf<uint32_t> err;
+  if ((rc = err.alloc(1))) return rc;
+  HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(uint32_t), stream));
+  HIP_TRY(launch_plan_pattern(rowptr, colind, n, nnz, P.d_m.p, P.d_c.p, err.p, stream));
+  P.h_m.resize(n);
+  uint32_t h_err = 0;
+  HIP_TRY(hipMemcpyAsync(P.h_m.data(), P.d_m.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&h_err, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (h_err & (PAT_ROWPTR | PAT_RANGE | PAT_ORDER | PAT_ASYM)) return SUBMAT_EPATTERN;
+  if (h_err & PAT_NODIAG) return SUBMAT_ENODIAG;
+  int maxm = 0;
+  for (int j = 0; j < n; ++j) maxm = std::max(maxm, P.h_m[j]);
+  if (maxm > SUBMAT_MAX_ORDER) return SUBMAT_ETOOBIG;
+
+  // buckets in longest-processing-time order (largest m first)
+  std::vector<int32_t> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return P.h_m[a] > P.h_m[b]; });
+  for (int32_t j : order) (P.h_m[j] <= P.small_max ? P.small_items : P.large_items).push_back(j);
+  P.small_mmax = P.small_items.empty() ? 0 : P.h_m[P.small_items.front()];
+  P.large_mmax = P.large_items.empty() ? 0 : P.h_m[P.large_items.front()];
+
+  // large-item layout: chunks bounded by the workspace budget
+  const int nl = (int)P.large_items.size();
+  std::vector<int32_t> ldm(nl);
+  std::vector<int64_t> off(nl), voff(nl), roff(nl), swoff(nl);
+  P.h_sqoff.resize(nl);
+  P.h_sdoff.resize(nl);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  double budget = g_opt.ws_bytes > 0 ? g_opt.ws_bytes : std::min<double>(0.4 * (double)free_b, 48.0 * (1ull << 30));
+  // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), rotations 16 (2 m^2 + 64)
+  int64_t sq = 0, sd = 0;
+  Chunk cur;
+  auto item_bytes = [&](int m, int ld) {
+    return 3 * 8 * (int64_t)ld * ld + 4 * 8 * (int64_t)ld + 16 * (2 * (int64_t)m * m + 64) + 4 * (3 * (6 * (int64_t)m + 16));
+  };
+  double used = 0;
+  for (int g = 0; g < nl; ++g) {
+    const int m = P.h_m[P.large_items[g]];
+    const int ld = (int)round_up(m, 16);
+    ldm[g] = ld;
+    const int64_t ib = item_bytes(m, ld);
+    if (cur.count > 0 && used + ib > budget) {
+      P.chunks.push_back(cur);
+      cur = Chunk();
+      used = 0;
+    }
+    if (cur.count == 0) cur.start = g;
+    off[g] = cur.slab_bytes;
+    voff[g] = cur.vec_bytes;
+    roff[g] = cur.rot_bytes;
+    swoff[g] = cur.sw_ints;
+    cur.slab_bytes += 8 * (int64_t)ld * ld;
+    cur.vec_bytes += 8 * (int64_t)ld;
+    cur.rot_bytes += 16 * (2 * (int64_t)m * m + 64);
+    cur.sw_ints += 3 * (6 * (int64_t)m + 16);
+    cur.max_m = std::max(cur.max_m, m);
+    cur.count++;
+    used += ib;
+    P.h_sqoff[g] = sq;
+    sq += 8 * (int64_t)ld * ld;
+  }
+  if (cur.count > 0) P.chunks.push_back(cur);
+  for (int g = 0; g < nl; ++g) {
+    P.h_sdoff[g] = sq + sd;
+    sd += 8 * (int64_t)ldm[g];
+  }
+  P.saved_q_bytes = sq;
+  P.saved_bytes = nl ? (sq + sd + 4 * (int64_t)nl) : 0;
+
+  int64_t ws_slab = 0, ws_vec = 0, ws_rot = 0, ws_sw = 0;
+  int max_count = 0;
+  for (auto& c : P.chunks) {
+    ws_slab = std::max(ws_slab, c.slab_bytes);
+    ws_vec = std::max(ws_vec, c.vec_bytes);
+    ws_rot = std::max(ws_rot, c.rot_bytes);
+    ws_sw = std::max(ws_sw, c.sw_ints);
+    max_count = std::max(max_count, c.count);
+  }
+  if ((rc = P.d_small.alloc(P.small_items.size())) || (rc = P.d_large.alloc(nl)) || (rc = P.d_ldm.alloc(nl)) ||
+      (rc = P.d_off.alloc(nl)) || (rc = P.d_voff.alloc(nl)) || (rc = P.d_roff.alloc(nl)) ||
+      (rc = P.d_swoff.alloc(nl)) || (rc = P.d_sqoff.alloc(nl)) || (rc = P.d_sdoff.alloc(nl)))
+    return rc;
+  if ((rc = P.S.alloc(ws_slab)) || (rc = P.Q.alloc(ws_slab)) || (rc = P.W.alloc(ws_slab)) ||
+      (rc = P.dv.alloc(ws_vec)) || (rc = P.ev.alloc(ws_vec)) || (rc = P.tv.alloc(ws_vec)) ||
+      (rc = P.rot.alloc(ws_rot)) || (rc = P.sweeps.alloc(ws_sw)) || (rc = P.nsweeps.alloc(max_count)) ||
+      (rc = P.flags.alloc(std::max(max_count, 1))))
+    return rc;
+  // one work counter per persistent launch of the longest sequence (the
+  // per-column path launches up to 7 kernels per column)
+  P.ncounters = 64 + 32 * (int)P.chunks.size() + 8 * n;
+  if ((rc = P.counters.alloc(P.ncounters))) return rc;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  HIP_TRY(up(P.d_small.p, P.small_items.data(), P.small_items.size() * 4));
+  HIP_TRY(up(P.d_large.p, P.large_items.data(), nl * 4));
+  HIP_TRY(up(P.d_ldm.p, ldm.data(), nl * 4));
+  HIP_TRY(up(P.d_off.p, off.data(), nl * 8));
+  HIP_TRY(up(P.d_voff.p, voff.data(), nl * 8));
+  HIP_TRY(up(P.d_roff.p, roff.data(), nl * 8));
+  HIP_TRY(up(P.d_swoff.p, swoff.data(), nl * 8));
+  HIP_TRY(up(P.d_sqoff.p, P.h_sqoff.data(), nl * 8));
+  HIP_TRY(up(P.d_sdoff.p, P.h_sdoff.data(), nl * 8));
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+  *out = plan.get();
+  g_plans.emplace(key, std::move(plan));
+  return SUBMAT_OK;
+}
+
+// ----------------------------------------------------------- launch sequence
+enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_FORMQ1, PH_QL, PH_ROT, PH_COLUMN, PH_ADJOINT, PH_FALLBACK, PH_N };
+
+struct Call {
+  const void* vals;
+  int vdtype;
+  int p;
+  int precision;
+  void* x;          // forward output
+  const void* gx;   // backward input
+  void* ga;         // backward output
+  char* saved;      // optional saved buffer
+  bool bwd;
+};
+
+struct Timer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  double ms[PH_N] = {0};
+  int launches[PH_N] = {0};
+  hipEvent_t a = nullptr, b = nullptr;
+  int start(int) {
+    if (!on) return SUBMAT_OK;
+    HIP_TRY(hipEventRecord(a, s));
+    return SUBMAT_OK;
+  }
+  int stop(int ph) {
+    if (!on) return SUBMAT_OK;
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, a, b));
+    ms[ph] += t;
+    launches[ph] += 1;
+    return SUBMAT_OK;
+  }
+};
+
+#define SEQ_TRY(expr)                   \
+  do {                                  \
+    int _r = (expr);                    \
+    if (_r != SUBMAT_OK) return _r;     \
+  } while (0)
+#define HIP_SEQ(ph, expr)                                  \
+  do {                                                     \
+    SEQ_TRY(tm.start(ph));                                 \
+    if ((expr) != hipSuccess) return SUBMAT_EHIP;          \
+    SEQ_TRY(tm.stop(ph));                                  \
+  } while (0)
+
+int persistent_grid(DeviceCtx* ctx, int n_items, int per_cu) {
+  int g = ctx->num_cus * per_cu;
+  if (g > n_items) g = n_items;
+  return g < 1 ? 1 : g;
+}
+
+LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, int max_m) {
+  LargeArgs a{};
+  a.rowptr = P.rowptr;
+  a.colind = P.colind;
+  a.vals = c.vals;
+  a.vdtype = c.vdtype;
+  a.items = P.d_large.p + g_first;
+  a.cidx = P.d_c.p;
+  a.ldm = P.d_ldm.p + g_first;
+  a.off = P.d_off.p + g_first;
+  a.voff = P.d_voff.p + g_first;
+  a.roff = P.d_roff.p + g_first;
+  a.swoff = P.d_swoff.p + g_first;
+  if (c.saved) {
+    a.qoff = P.d_sqoff.p + g_first;
+    a.doff = P.d_sdoff.p + g_first;
+    a.Q = c.saved;
+    a.d = c.saved;
+  } else {
+    a.qoff = P.d_off.p + g_first;
+    a.doff = P.d_voff.p + g_first;
+    a.Q = P.Q.p;
+    a.d = P.dv.p;
+  }
+  a.n_items = count;
+  a.max_m = max_m;
+  a.S = P.S.p;
+  a.W = P.W.p;
+  a.e = P.ev.p;
+  a.tau = P.tv.p;
+  a.rot = P.rot.p;
+  a.sweeps = P.sweeps.p;
+  a.nsweeps = P.nsweeps.p + (g_first - P.chunks[chunk].start);
+  a.flags = (c.saved ? (int32_t*)(c.saved + P.saved_bytes - 4 * (int64_t)P.large_items.size()) + g_first
+                     : P.flags.p + (g_first - P.chunks[chunk].start));
+  a.p = c.p;
+  a.kappa_max = g_opt.kappa_max;
+  a.rot_batch = g_opt.rot_batch;
+  a.x = c.x;
+  a.gx = c.gx;
+  a.ga = c.ga;
+  return a;
+}
+
+// One pass of the large-order pipeline over items [g_first, g_first+count)
+// of `chunk`, in FP64 or FP32. `only_flagged` restricts it to the items the
+// FP32 pass sent to FP64. With a saved buffer in the backward, only the
+// adjoint runs.
+int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, int& ctr, int chunk, int g_first,
+              int count, int max_m, int fp64, int only_flagged, bool per_column) {
+  LargeArgs a = make_large(P, c, chunk, g_first, count, max_m);
+  a.status = ctx->status.p;
+  a.fp64 = fp64;
+  a.only_flagged = only_flagged;
+  const int tune_cu = per_column ? 0 : tuned_blocks_per_cu(max_m, fp64);
+  a.grid = per_column ? 1 : persistent_grid(ctx, count, tune_cu);
+  const int ph = only_flagged ? PH_FALLBACK : -1;
+  auto next = [&]() { a.work_ctr = P.counters.p + (ctr++ % P.ncounters); };
+  const bool eig = !(c.bwd && c.saved);
+  if (eig) {
+    next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_FORMQ1 : ph, launch_form_q1(a, s));
+    HIP_SEQ(ph < 0 ? PH_QL : ph, launch_tridiag_ql(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_ROT : ph, launch_apply_rotations(a, s));
+  }
+  next();
+  if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(a, s));
+  else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(a, s));
+  return SUBMAT_OK;
+}
+
+int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm) {
+  int ctr = 0;
+  HIP_SEQ(PH_RESET, launch_reset_status(ctx->status.p, P.counters.p, P.ncounters, s));
+  if (c.bwd) HIP_SEQ(PH_RESET, launch_fill_zero(c.ga, P.nnz * (c.vdtype == 0 ? 8 : 4), s));
+  const bool plain = c.precision == SUBMAT_PREC_F64_PLAIN;
+  const int mixed = c.precision == SUBMAT_PREC_F32_MIXED;
+  // small-order bucket
+  if (!P.small_items.empty()) {
+    SmallArgs sa{};
+    sa.rowptr = P.rowptr;
+    sa.colind = P.colind;
+    sa.vals = c.vals;
+    sa.vdtype = c.vdtype;
+    sa.cidx = P.d_c.p;
+    sa.p = c.p;
+    sa.mixed = mixed;
+    sa.kappa_max = g_opt.kappa_max;
+    sa.x = c.bwd ? nullptr : c.x;
+    sa.gx = c.bwd ? c.gx : nullptr;
+    sa.ga = c.bwd ? c.ga : nullptr;
+    sa.status = ctx->status.p;
+    if (!plain) {
+      sa.items = P.d_small.p;
+      sa.n_items = (int)P.small_items.size();
+      sa.mmax = P.small_mmax;
+      sa.grid = persistent_grid(ctx, sa.n_items, 8);
+      sa.work_ctr = P.counters.p + (ctr++ % P.ncounters);
+      HIP_SEQ(PH_SMALL, launch_small(sa, s));
+    } else {
+      for (size_t i = 0; i < P.small_items.size(); ++i) {
+        sa.items = P.d_small.p + i;
+        sa.n_items = 1;
+        sa.mmax = P.h_m[P.small_items[i]];
+        sa.grid = 1;
+        sa.work_ctr = P.counters.p + (ctr++ % P.ncounters);
+        HIP_SEQ(PH_SMALL, launch_small(sa, s));
+      }
+    }
+  }
+  // large-order bucket, chunk by chunk
+  for (int ci = 0; ci < (int)P.chunks.size(); ++ci) {
+    const Chunk& ch = P.chunks[ci];
+    if (plain) {
+      for (int g = ch.start; g < ch.start + ch.count; ++g)
+        SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, g, 1, P.h_m[P.large_items[g]], 1, 0, true));
+    } else if (!mixed) {
+      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 0, false));
+    } else {
+      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 0, 0, false));
+      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 1, false));
+    }
+  }
+  return SUBMAT_OK;
+}
+
+int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
+  std::vector<uintptr_t> key = {(uintptr_t)c.vals, (uintptr_t)c.vdtype, (uintptr_t)c.p, (uintptr_t)c.precision,
+                                (uintptr_t)c.x, (uintptr_t)c.gx, (uintptr_t)c.ga, (uintptr_t)c.saved,
+                                (uintptr_t)c.bwd, (uintptr_t)(g_opt.kappa_max * 1e3), (uintptr_t)g_opt.rot_batch};
+  GraphEntry* hit = nullptr;
+  for (auto& g : P.graphs)
+    if (g.key == key) hit = &g;
+  if (!hit) {
+    if (P.graphs.size() >= 8) {
+      auto old = std::min_element(P.graphs.begin(), P.graphs.end(),
+                                  [](const GraphEntry& a, const GraphEntry& b) { return a.stamp < b.stamp; });
+      if (old->exec) (void)hipGraphExecDestroy(old->exec);
+      if (old->graph) (void)hipGraphDestroy(old->graph);
+      P.graphs.erase(old);
+    }
+    GraphEntry ge;
+    ge.key = key;
+    Timer off;
+    HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = run_sequence(P, ctx, c, P.cap_stream, off);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(P.cap_stream, &graph);
+    if (rc != SUBMAT_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess) return SUBMAT_EHIP;
+    ge.graph = graph;
+    if (hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return SUBMAT_EHIP;
+    }
+    P.graphs.push_back(ge);
+    hit = &P.graphs.back();
+  }
+  hit->stamp = ++P.stamp;
+  HIP_TRY(hipGraphLaunch(hit->exec, s));
+  return SUBMAT_OK;
+}
+
+int check_args(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz, int32_t p,
+               int32_t dtype, int32_t precision) {
+  if (!rowptr || !colind || !vals) return SUBMAT_EINVAL;
+  if (n < 1 || nnz < n || p < 1) return SUBMAT_EINVAL;
+  if (dtype != SUBMAT_F64 && dtype != SUBMAT_F32) return SUBMAT_EINVAL;
+  if (precision < SUBMAT_PREC_F64 || precision > SUBMAT_PREC_F64_PLAIN) return SUBMAT_EINVAL;
+  if (nnz > (int64_t)INT32_MAX) return SUBMAT_EINVAL;
+  return SUBMAT_OK;
+}
+
+int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, Call& c, void* stream,
+             Timer* timer) {
+  DeviceCtx* ctx = nullptr;
+  SEQ_TRY(get_ctx(&ctx));
+  hipStream_t s = (hipStream_t)stream;
+  Plan* P = nullptr;
+  SEQ_TRY(build_plan(rowptr, colind, n, nnz, s, ctx, &P));
+  if (c.saved && c.precision == SUBMAT_PREC_F64_PLAIN) c.saved = nullptr;
+  if (timer) {
+    timer->s = s;
+    timer->on = true;
+    HIP_TRY(hipEventCreate(&timer->a));
+    HIP_TRY(hipEventCreate(&timer->b));
+    int rc = run_sequence(*P, ctx, c, s, *timer);
+    (void)hipEventDestroy(timer->a);
+    (void)hipEventDestroy(timer->b);
+    return rc;
+  }
+  if (g_opt.use_graph && c.precision != SUBMAT_PREC_F64_PLAIN) return launch_graph(*P, ctx, c, s);
+  Timer off;
+  return run_sequence(*P, ctx, c, s, off);
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                       int32_t p, int32_t dtype, int32_t precision, void* x_vals, void* saved, void* stream) {
+  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
+  if (rc) return rc;
+  if (!x_vals) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Call c{vals, dtype, p, precision, x_vals, nullptr, nullptr, (char*)saved, false};
+  return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
+}
+
+int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                       int32_t p, int32_t dtype, int32_t precision, const void* grad_x, void* grad_a,
+                       const void* saved, void* stream) {
+  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
+  if (rc) return rc;
+  if (!grad_x || !grad_a) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Call c{vals, dtype, p, precision, nullptr, grad_x, grad_a, (char*)saved, true};
+  return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
+}
+
+int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, int32_t dtype,
+                           int32_t precision) {
+  if (!rowptr || !colind || n < 1 || nnz < n) return SUBMAT_EINVAL;
+  if (dtype != SUBMAT_F64 && dtype != SUBMAT_F32) return SUBMAT_EINVAL;
+  (void)precision;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* ctx = nullptr;
+  int rc = get_ctx(&ctx);
+  if (rc) return rc;
+  Plan* P = nullptr;
+  rc = build_plan(rowptr, colind, n, nnz, nullptr, ctx, &P);
+  if (rc) return rc;
+  return P->saved_bytes;
+}
+
+int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallback, int64_t* n_unconverged) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* ctx = nullptr;
+  int rc = get_ctx(&ctx);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int64_t h[ST_NSLOTS] = {0};
+  HIP_TRY(hipMemcpy(h, ctx->status.p, sizeof(h), hipMemcpyDeviceToHost));
+  if (n_nonpositive) *n_nonpositive = h[ST_NONPOS];
+  if (n_fallback) *n_fallback = h[ST_FALLBACK];
+  if (n_unconverged) *n_unconverged = h[ST_UNCONV];
+  return SUBMAT_OK;
+}
+
+int submat_set_option(int32_t key, double value) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  switch (key) {
+    case SUBMAT_OPT_KAPPA_MAX:
+      if (!(value > 1.0)) return SUBMAT_EINVAL;
+      g_opt.kappa_max = value;
+      return SUBMAT_OK;
+    case SUBMAT_OPT_USE_GRAPH:
+      g_opt.use_graph = value != 0.0;
+      return SUBMAT_OK;
+    case SUBMAT_OPT_SMALL_MAX:
+      if (value < 1 || value > 64) return SUBMAT_EINVAL;
+      g_opt.small_max = (int)value;
+      g_plans.clear();
+      return SUBMAT_OK;
+    case SUBMAT_OPT_WS_BYTES:
+      if (value < 0) return SUBMAT_EINVAL;
+      g_opt.ws_bytes = value;
+      g_plans.clear();
+      return SUBMAT_OK;
+    case SUBMAT_OPT_ROT_BATCH:
+      if (value != 8 && value != 16) return SUBMAT_EINVAL;
+      g_opt.rot_batch = (int)value;
+      return SUBMAT_OK;
+    default:
+      return SUBMAT_EINVAL;
+  }
+}
+
+double submat_get_option(int32_t key) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  switch (key) {
+    case SUBMAT_OPT_KAPPA_MAX: return g_opt.kappa_max;
+    case SUBMAT_OPT_USE_GRAPH: return g_opt.use_graph;
+    case SUBMAT_OPT_SMALL_MAX: return g_opt.small_max;
+    case SUBMAT_OPT_WS_BYTES: return g_opt.ws_bytes;
+    case SUBMAT_OPT_ROT_BATCH: return g_opt.rot_batch;
+    default: return NAN;
+  }
+}
+
+const char* submat_strerror(int32_t code) {
+  switch (code) {
+    case SUBMAT_OK: return "ok";
+    case SUBMAT_EINVAL: return "invalid argument";
+    case SUBMAT_EPATTERN: return "invalid or asymmetric sparsity pattern";
+    case SUBMAT_ENODIAG: return "diagonal entry not stored";
+    case SUBMAT_ENOMEM: return "device allocation failed";
+    case SUBMAT_EHIP: return "HIP runtime error";
+    case SUBMAT_ETOOBIG: return "submatrix order exceeds SUBMAT_MAX_ORDER";
+    case SUBMAT_ESAVED: return "saved buffer does not match";
+    default: return "unknown status code";
+  }
+}
+
+void submat_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  (void)hipDeviceSynchronize();
+  g_plans.clear();
+}
+
+int32_t submat_version(void) { return 100; }
+
+int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                       int32_t p, int32_t dtype, int32_t precision, void* x_vals, const void* grad_x, void* grad_a,
+                       void* stream, double* phase_ms, int32_t* phase_launches) {
+  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
+  if (rc) return rc;
+  if (!x_vals || !phase_ms || !phase_launches) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Timer tm;
+  Call c{vals, dtype, p, precision, x_vals, nullptr, nullptr, nullptr, false};
+  rc = run_call(rowptr, colind, n, nnz, c, stream, &tm);
+  if (rc) return rc;
+  if (grad_x && grad_a) {
+    Call cb{vals, dtype, p, precision, nullptr, grad_x, grad_a, nullptr, true};
+    rc = run_call(rowptr, colind, n, nnz, cb, stream, &tm);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < SUBMAT_NUM_PHASES; ++i) {
+    phase_ms[i] = tm.ms[i];
+    phase_launches[i] = tm.launches[i];
+  }
+  return SUBMAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Tuning table for the persistent large-order launches.
+//
+// The table maps an upper bound on the submatrix order to the number of
+// workgroups per compute unit, separately for FP64 and FP32. Defaults come
+// from LDS and register use of the kernels; a file written by the package's
+// autotune script (environment variable SUBMAT_TUNE_FILE, lines
+// "fp64 m_hi blocks_per_cu") overrides them.
+#include <cstdio>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
+#include "autotune.hpp"
+
+namespace submat {
+namespace {
+
+struct Entry {
+  int fp64, m_hi, bpc;
+};
+
+std::vector<Entry> g_table;
+bool g_loaded = false;
+std::mutex g_tmu;
+
+void load_locked() {
+  g_table = {{1, 128, 8}, {1, 256, 4}, {1, 1024, 2}, {1, 1 << 30, 1},
+             {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1}};
+  const char* path = std::getenv("SUBMAT_TUNE_FILE");
+  if (path && *path) {
+    if (FILE* f = std::fopen(path, "r")) {
+      std::vector<Entry> t;
+      Entry e;
+      while (std::fscanf(f, "%d %d %d", &e.fp64, &e.m_hi, &e.bpc) == 3)
+        if (e.bpc >= 1 && e.bpc <= 32 && e.m_hi >= 1) t.push_back(e);
+      std::fclose(f);
+      if (!t.empty()) g_table = t;
+    }
+  }
+  g_loaded = true;
+}
+
+}  // namespace
+
+void reload_tuning() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  load_locked();
+}
+
+int tuned_blocks_per_cu(int max_m, int fp64) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_loaded) load_locked();
+  int best = 1, best_hi = 1 << 30;
+  bool found = false;
+  for (const Entry& e : g_table) {
+    if (e.fp64 != (fp64 ? 1 : 0) || max_m > e.m_hi) continue;
+    if (!found || e.m_hi < best_hi) {
+      best = e.bpc;
+      best_hi = e.m_hi;
+      found = true;
+    }
+  }
+  return best;
+}
+
+}  // namespace submat

@@ -1,0 +1,107 @@
+// Host-side launch interface between the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace submat {
+
+// Status counter slots (int64 each) in the per-device status block.
+enum StatusSlot : int {
+  ST_NONPOS = 0,      // submatrices with an eigenvalue <= 0
+  ST_FALLBACK = 1,    // submatrices redone in FP64 by the mixed path
+  ST_UNCONV = 2,      // eigensolver did not converge
+  ST_NSLOTS = 64,
+};
+
+
+// Pattern error bits written by the plan kernel.
+enum PatternBits : uint32_t {
+  PAT_ROWPTR = 1u,   // rowptr not 0..nnz non-decreasing
+  PAT_RANGE = 2u,    // column index out of range
+  PAT_ORDER = 4u,    // row not strictly increasing
+  PAT_ASYM = 8u,     // (i,j) stored but (j,i) not
+  PAT_NODIAG = 16u,  // diagonal not stored
+};
+
+// ---- plan / utility kernels (plan.hip) ----
+hipError_t launch_plan_pattern(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz,
+                               int32_t* m_out, int32_t* c_out, uint32_t* err, hipStream_t s);
+hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t s);
+hipError_t launch_reset_status(int64_t* status, int32_t* counters, int ncounters, hipStream_t s);
+
+// ---- one-wavefront Jacobi path (small.hip) ----
+struct SmallArgs {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const void* vals;      // value type vdtype
+  int vdtype;            // 0 = f64, 1 = f32
+  const int32_t* items;  // columns on this path, largest m first
+  const int32_t* cidx;   // c_j per column
+  int n_items;
+  int mmax;              // largest m among items
+  int p;
+  int mixed;             // 1: FP32 bulk with FP64 redo of flagged submatrices
+  double kappa_max;
+  void* x;               // forward output (nullptr in backward)
+  const void* gx;        // backward input (nullptr in forward)
+  void* ga;              // backward output, accumulated (zeroed by the caller)
+  int64_t* status;
+  int32_t* work_ctr;     // zeroed before the launch
+  int grid;              // persistent grid size
+};
+hipError_t launch_small(const SmallArgs& a, hipStream_t s);
+
+// ---- large-order path (large.hip) ----
+struct LargeArgs {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const void* vals;
+  int vdtype;
+  const int32_t* items;   // chunk items -> column id
+  const int32_t* cidx;    // c_j per column
+  const int32_t* ldm;     // per item: leading dimension (padded order)
+  // All offsets are in BYTES, so an FP32 and an FP64 view of one slot start
+  // at the same address.
+  const int64_t* off;     // per item: S and W slab offset
+  const int64_t* qoff;    // per item: Q slab offset (workspace or saved buffer)
+  const int64_t* voff;    // per item: offset of its e / tau vectors
+  const int64_t* doff;    // per item: offset of d (eigenvalues after QL)
+  const int64_t* roff;    // per item: offset of its rotation pairs
+  const int64_t* swoff;   // per item: offset (in int32 units) in the sweep table
+  int n_items;
+  int max_m;
+  void* S;                // slab base (Householder vectors, later scratch)
+  void* Q;                // slab base (eigenvectors)
+  void* W;                // slab base (adjoint scratch)
+  void* d;                // per item vectors (eigenvalues after QL)
+  void* e;
+  void* tau;
+  void* rot;              // rotation pairs (c, s)
+  int32_t* sweeps;        // per sweep: hi, lo, rotation offset (3 ints)
+  int32_t* nsweeps;       // per item
+  int32_t* flags;         // per item: bit0 nonpositive, bit1 fallback, bit2 unconverged
+  int p;
+  double kappa_max;
+  int rot_batch;
+  void* x;                // forward output (value type vdtype)
+  const void* gx;         // backward input
+  void* ga;               // backward output (accumulated)
+  int64_t* status;
+  int32_t* work_ctr;
+  int grid;
+  int fp64;               // 1: compute in FP64, 0: FP32
+  int only_flagged;       // 1: process only items whose fallback flag is set
+};
+enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
+
+hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
+hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
+hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s);
+hipError_t launch_tridiag_ql(const LargeArgs& a, hipStream_t s);
+hipError_t launch_apply_rotations(const LargeArgs& a, hipStream_t s);
+hipError_t launch_check_spectrum(const LargeArgs& a, hipStream_t s);
+hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s);
+
+}  // namespace submat

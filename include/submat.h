@@ -135,6 +135,15 @@ int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t
 int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallback,
                         int64_t* n_unconverged);
 
+/*
+ * Synchronises `stream` and copies the first n (n <= 8) device counters of the
+ * last completed call on the current device: [0] non-positive submatrices,
+ * [1] FP64 redos, [2] unconverged, [3] the sum over large-order submatrices of
+ * (recorded QL rotations x order), i.e. the row updates the rotation kernel
+ * applies (6 flops each). Returns SUBMAT_EINVAL for n outside 1..8 or out NULL.
+ */
+int submat_query_counters(void* stream, int64_t* out, int32_t n);
+
 /* Options (process-wide). Unknown keys return SUBMAT_EINVAL. */
 int submat_set_option(int32_t key, double value);
 double submat_get_option(int32_t key);

@@ -49,6 +49,7 @@ SIGNATURES = {
     "submat_invroot_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P]),
     "submat_saved_bytes": (_I64, [_P, _P, _I32, _I64, _I32, _I32]),
     "submat_query_status": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "submat_query_counters": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _I32]),
     "submat_set_option": (ctypes.c_int, [_I32, ctypes.c_double]),
     "submat_get_option": (ctypes.c_double, [_I32]),
     "submat_strerror": (ctypes.c_char_p, [_I32]),
@@ -120,6 +121,12 @@ def submat_query_status(stream) -> dict:
     _check(load().submat_query_status(stream, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
            "submat_query_status")
     return {"nonpositive": a.value, "fallback": b.value, "unconverged": c.value}
+
+
+def submat_query_counters(stream, n: int = 4) -> list:
+    buf = (_I64 * n)()
+    _check(load().submat_query_counters(stream, buf, n), "submat_query_counters")
+    return list(buf)
 
 
 def submat_set_option(key: int, value: float) -> None:

@@ -56,6 +56,7 @@ struct DevBuf {
 struct DeviceCtx {
   int device = -1;
   int num_cus = 0;
+  int lds_limit = 65536;
   DevBuf<int64_t> status;      // ST_NSLOTS slots
   std::vector<int64_t> last_status;
 };
@@ -71,6 +72,7 @@ int get_ctx(DeviceCtx** out) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     ctx->num_cus = prop.multiProcessorCount;
+    ctx->lds_limit = (int)prop.sharedMemPerBlock;
     int rc = ctx->status.alloc(ST_NSLOTS);
     if (rc) return rc;
     HIP_TRY(hipMemset(ctx->status.p, 0, ST_NSLOTS * sizeof(int64_t)));
@@ -187,7 +189,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   P.h_sdoff.resize(nl);
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-  double budget = g_opt.ws_bytes > 0 ? g_opt.ws_bytes : std::min<double>(0.4 * (double)free_b, 48.0 * (1ull << 30));
+  double budget = g_opt.ws_bytes > 0 ? g_opt.ws_bytes : 0.5 * (double)free_b;
   // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), rotations 16 (2 m^2 + 64)
   int64_t sq = 0, sd = 0;
   Chunk cur;
@@ -378,6 +380,8 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
               int count, int max_m, int fp64, int only_flagged, bool per_column) {
   LargeArgs a = make_large(P, c, chunk, g_first, count, max_m);
   a.status = ctx->status.p;
+  a.lds_limit = ctx->lds_limit;
+  a.ql_bpc = tuned_ql_blocks_per_cu(max_m);
   a.fp64 = fp64;
   a.only_flagged = only_flagged;
   const int tune_cu = per_column ? 0 : tuned_blocks_per_cu(max_m, fp64);
@@ -578,6 +582,17 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
   if (n_nonpositive) *n_nonpositive = h[ST_NONPOS];
   if (n_fallback) *n_fallback = h[ST_FALLBACK];
   if (n_unconverged) *n_unconverged = h[ST_UNCONV];
+  return SUBMAT_OK;
+}
+
+int submat_query_counters(void* stream, int64_t* out, int32_t n) {
+  if (!out || n < 1 || n > 8) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* ctx = nullptr;
+  int rc = get_ctx(&ctx);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(out, ctx->status.p, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost));
   return SUBMAT_OK;
 }
 

@@ -1,10 +1,11 @@
 // Tuning table for the persistent large-order launches.
 //
 // The table maps an upper bound on the submatrix order to the number of
-// workgroups per compute unit, separately for FP64 and FP32. Defaults come
-// from LDS and register use of the kernels; a file written by the package's
-// autotune script (environment variable SUBMAT_TUNE_FILE, lines
-// "fp64 m_hi blocks_per_cu") overrides them.
+// workgroups per compute unit: kind 0 = FP32 persistent kernels, kind 1 =
+// FP64 persistent kernels, kind 2 = QL kernel. Defaults come from LDS and
+// register use of the kernels; a file written by the package's autotune
+// script (environment variable SUBMAT_TUNE_FILE, lines
+// "kind m_hi blocks_per_cu") overrides them.
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -25,14 +26,15 @@ std::mutex g_tmu;
 
 void load_locked() {
   g_table = {{1, 128, 8}, {1, 256, 4}, {1, 1024, 2}, {1, 1 << 30, 1},
-             {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1}};
+             {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1},
+             {2, 1 << 30, 2}};
   const char* path = std::getenv("SUBMAT_TUNE_FILE");
   if (path && *path) {
     if (FILE* f = std::fopen(path, "r")) {
       std::vector<Entry> t;
       Entry e;
       while (std::fscanf(f, "%d %d %d", &e.fp64, &e.m_hi, &e.bpc) == 3)
-        if (e.bpc >= 1 && e.bpc <= 32 && e.m_hi >= 1) t.push_back(e);
+        if (e.bpc >= 1 && e.bpc <= 32 && e.m_hi >= 1 && e.fp64 >= 0 && e.fp64 <= 2) t.push_back(e);
       std::fclose(f);
       if (!t.empty()) g_table = t;
     }
@@ -47,13 +49,13 @@ void reload_tuning() {
   load_locked();
 }
 
-int tuned_blocks_per_cu(int max_m, int fp64) {
+static int lookup(int kind, int max_m) {
   std::lock_guard<std::mutex> lk(g_tmu);
   if (!g_loaded) load_locked();
   int best = 1, best_hi = 1 << 30;
   bool found = false;
   for (const Entry& e : g_table) {
-    if (e.fp64 != (fp64 ? 1 : 0) || max_m > e.m_hi) continue;
+    if (e.fp64 != kind || max_m > e.m_hi) continue;
     if (!found || e.m_hi < best_hi) {
       best = e.bpc;
       best_hi = e.m_hi;
@@ -62,5 +64,9 @@ int tuned_blocks_per_cu(int max_m, int fp64) {
   }
   return best;
 }
+
+int tuned_blocks_per_cu(int max_m, int fp64) { return lookup(fp64 ? 1 : 0, max_m); }
+
+int tuned_ql_blocks_per_cu(int max_m) { return lookup(2, max_m); }
 
 }  // namespace submat

@@ -11,6 +11,7 @@ enum StatusSlot : int {
   ST_NONPOS = 0,      // submatrices with an eigenvalue <= 0
   ST_FALLBACK = 1,    // submatrices redone in FP64 by the mixed path
   ST_UNCONV = 2,      // eigensolver did not converge
+  ST_ROTWORK = 3,     // sum of (recorded QL rotations x order): row updates of the rotation kernel
   ST_NSLOTS = 64,
 };
 
@@ -84,6 +85,9 @@ struct LargeArgs {
   int p;
   double kappa_max;
   int rot_batch;
+  int ql_items;           // submatrices per wave in the QL kernel (set at launch)
+  int lds_limit;          // device limit on LDS bytes per workgroup
+  int ql_bpc;             // QL blocks per compute unit (tuning table)
   void* x;                // forward output (value type vdtype)
   const void* gx;         // backward input
   void* ga;               // backward output (accumulated)

@@ -1,36 +1,53 @@
 // Large-order path (m > 64): one workgroup per submatrix for the dense
 // stages, one lane per submatrix for the tridiagonal QL iteration.
 //
-//   gather     S_j from CSR into an HBM slab (Section 3.1), symmetrised
-//   tridiag    Householder reduction S = Q1 T Q1^T (lower form)
-//   form_q1    Q1 accumulated explicitly from the reflectors
-//   ql         implicit QL with Wilkinson shifts on T; the eigenvalues replace
-//              d and every plane rotation is recorded, sweep by sweep
-//   rotations  Q = Q1 * (all rotations): each thread owns rows of Q and applies
-//              a batch of K sweeps in one pass over the row (sweep s lags
-//              sweep s-1 by two columns, so a window of 2K values suffices)
-//   column     x = Q (f(lambda) o Q[c,:]^T) into X's value segment
-//              (Sections 3.3-3.4)
-//   adjoint    D = Q sym(G o (a b^T)) Q^T scattered into dA's stored pairs
+//   gather      S_j from CSR into an HBM slab (Section 3.1), symmetrised
+//   tridiag     blocked Householder reduction S = Q1 T Q1^T (lower form): per
+//               panel of NB columns a lower-triangle symv per column, and one
+//               rank-2*NB trailing update on MFMA (lower tiles only)
+//   form_q1     Q1 accumulated explicitly from compact-WY blocks of NB
+//               reflectors, products on MFMA
+//   ql          implicit QL with Wilkinson shifts on T (d, e in LDS); the
+//               eigenvalues replace d and every plane rotation is recorded,
+//               sweep by sweep
+//   rotations   Q = Q1 * (all rotations): each thread owns a row of Q and
+//               applies a batch of K sweeps in one pass over it (sweep s lags
+//               sweep s-1 by two columns, so a window of 2K values suffices);
+//               rotation coefficients are staged in LDS tables
+//   column      x = Q (f(lambda) o Q[c,:]^T) into X's value segment
+//               (Sections 3.3-3.4)
+//   adjoint     D = Q sym(G o (a b^T)) Q^T on MFMA, scattered into dA's
+//               stored pairs
 //
 // Slabs are column-major with leading dimension ldm (the order rounded up
-// to a multiple of 16); element (r, c) of item i is at base + off[i] +
-// c*ldm + r.
+// to a multiple of 16). After the reduction only the lower triangle of the
+// working matrix is meaningful, and column k of the S slab holds the full
+// Householder vector v_k (zeros above row k+1, 1 at row k+1).
 #include <math.h>
 
 #include "common.hpp"
+#include "gemm.hpp"
 #include "kernels.hpp"
 
 namespace submat {
 
 constexpr int kBlock = 256;
 constexpr int kNW = kBlock / kWave;
+constexpr int kBigBlock = 512;
+constexpr int kBigNW = kBigBlock / kWave;
+constexpr int kNB = 32;  // panel width of the reduction and of the WY blocks
 
 template <class T> __device__ __forceinline__ T* at(void* base, int64_t off_bytes) {
   return (T*)((char*)base + off_bytes);
 }
 template <class T> __device__ __forceinline__ const T* at(const void* base, int64_t off_bytes) {
   return (const T*)((const char*)base + off_bytes);
+}
+
+__device__ __forceinline__ bool skip_item(const LargeArgs& a, int it) {
+  const int fl = a.flags[it];
+  if (a.only_flagged) return !(fl & LF_FALLBACK);
+  return !a.fp64 && (fl & LF_FALLBACK);  // the FP32 pass leaves flagged items to FP64
 }
 
 // ---------------------------------------------------------------- gather
@@ -74,16 +91,26 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
 }
 
 // ------------------------------------------------------- tridiagonalise
-// Unblocked Householder reduction, both triangles kept up to date.
-// Step k: v (v0 = 1) maps S[k+1:, k] to beta e_1; p = tau S22 v;
-// w = p - (tau/2)(p.v) v; S22 -= v w^T + w v^T.
-// Outputs: d[0..m), e[0..m-1), tau[0..m-2), v_k stored in S[k+1:, k].
+// Blocked Householder reduction (lower form), panel width NB. Within a
+// panel, column k = k0 + i is first brought up to date with the panel's
+// earlier vectors (A[k:, k] -= V W[k,:]^T + W V[k,:]^T), its reflector
+// (v, tau, beta) is formed, and w = tau (A22 v - V (W^T v) - W (V^T v)),
+// w -= (tau/2)(w.v) v, where A22 is the trailing matrix as it stood at the
+// start of the panel (lower triangle only). After the panel,
+// A22 -= V W^T + W V^T on MFMA.
+// Outputs: d[0..m), e[0..m-1), tau[0..m-2) and v_k in column k of S.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_tridiagonalise(LargeArgs a) {
+__global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
-  __shared__ double red[kNW];
-  const int tid = threadIdx.x;
+  __shared__ double red[kBigNW];
+  __shared__ double vk[kNB], wk[kNB], z1[kNB], z2[kNB];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  double* sv = dyn;                     // v (max_m)
+  double* sy = dyn + a.max_m;           // y = A22 v (max_m)
+  double* sdot = dyn + 2 * a.max_m;     // column dots of the symv (max_m)
+  double* spart = dyn + 3 * a.max_m;    // row partials of waves 0..3 (4 x max_m)
+  T* gsm = (T*)(dyn + 7 * a.max_m);
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -92,60 +119,188 @@ __global__ __launch_bounds__(kBlock) void k_tridiagonalise(LargeArgs a) {
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
     T* S = at<T>(a.S, a.off[it]);
+    T* Wb = at<T>(a.W, a.off[it]);  // W: column c at Wb + c*ld, rows indexed globally
     T* d = at<T>(a.d, a.doff[it]);
     T* e = at<T>(a.e, a.voff[it]);
     T* tau = at<T>(a.tau, a.voff[it]);
-    T* sv = (T*)dyn;
-    T* sw = sv + a.max_m;
-    for (int k = 0; k + 2 < m; ++k) {
-      const int n2 = m - k - 1;
-      T* x = S + (int64_t)k * ld + (k + 1);
-      double part = 0.0;
-      for (int i = 1 + tid; i < n2; i += kBlock) part += (double)x[i] * (double)x[i];
-      const double alpha = (double)x[0];  // read before the barrier: x[0] is overwritten below
-      const double sigma = block_sum<kNW>(part, red);
-      double beta, tk, scale;
-      if (sigma == 0.0) {
-        beta = alpha; tk = 0.0; scale = 0.0;
-      } else {
-        const double nrm = sqrt(alpha * alpha + sigma);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tk = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      for (int i = tid; i < n2; i += kBlock) {
-        const T vi = (i == 0) ? T(1) : (T)((double)x[i] * scale);
-        sv[i] = vi;
-        x[i] = vi;
-      }
-      if (tid == 0) {
-        d[k] = S[(int64_t)k * ld + k];
-        e[k] = (T)beta;
-        tau[k] = (T)tk;
-      }
-      __syncthreads();
-      if (tk != 0.0) {
-        // p = tau * S22 v (thread per row)
-        T* S22 = S + (int64_t)(k + 1) * ld + (k + 1);
-        double pv_part = 0.0;
-        for (int i = tid; i < n2; i += kBlock) {
-          T acc = T(0);
-          for (int jj = 0; jj < n2; ++jj) acc += S22[(int64_t)jj * ld + i] * sv[jj];
-          const T pi = (T)tk * acc;
-          sw[i] = pi;
-          pv_part += (double)pi * (double)sv[i];
-        }
-        const double Kc = 0.5 * tk * block_sum<kNW>(pv_part, red);
-        for (int i = tid; i < n2; i += kBlock) sw[i] = (T)((double)sw[i] - Kc * (double)sv[i]);
-        __syncthreads();
-        for (int i = tid; i < n2; i += kBlock) {
-          const T vi = sv[i], wi = sw[i];
-          for (int jj = 0; jj < n2; ++jj) {
-            T* q = S22 + (int64_t)jj * ld + i;
-            *q = *q - (vi * sw[jj] + wi * sv[jj]);
+    for (int k0 = 0; k0 + 2 < m; k0 += kNB) {
+      const int nbt = (m - 2 - k0) < kNB ? (m - 2 - k0) : kNB;
+      for (int i = 0; i < nbt; ++i) {
+        const int k = k0 + i;
+        const int n2 = m - k - 1;
+        // (1) bring column k (rows k..m-1) up to date with the panel's vectors
+        if (i > 0) {
+          if (tid < i) {
+            vk[tid] = (double)S[(int64_t)(k0 + tid) * ld + k];
+            wk[tid] = (double)Wb[(int64_t)tid * ld + k];
           }
+          __syncthreads();
+          for (int r = k + tid; r < m; r += kBigBlock) {
+            double acc = (double)S[(int64_t)k * ld + r];
+#pragma unroll 1
+            for (int c = 0; c < i; ++c)
+              acc -= (double)S[(int64_t)(k0 + c) * ld + r] * wk[c] + (double)Wb[(int64_t)c * ld + r] * vk[c];
+            S[(int64_t)k * ld + r] = (T)acc;
+          }
+          __syncthreads();
+        }
+        // (2) reflector from x = A[k+1:, k]
+        T* x = S + (int64_t)k * ld + (k + 1);
+        double part = 0.0;
+        for (int q = 1 + tid; q < n2; q += kBigBlock) part += (double)x[q] * (double)x[q];
+        const double alpha = (double)x[0];   // read before the barrier: x[0] is overwritten below
+        const double dkk = (double)S[(int64_t)k * ld + k];
+        const double sigma = block_sum<kBigNW>(part, red);
+        double beta, tk, scale;
+        if (sigma == 0.0) {
+          beta = alpha; tk = 0.0; scale = 0.0;
+        } else {
+          const double nrm = sqrt(alpha * alpha + sigma);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tk = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        for (int q = tid; q < n2; q += kBigBlock) {
+          const double vq = (q == 0) ? 1.0 : (double)x[q] * scale;
+          sv[q] = vq;
+          x[q] = (T)vq;
+        }
+        if (tid == 0) {
+          d[k] = (T)dkk;
+          e[k] = (T)beta;
+          tau[k] = (T)tk;
         }
         __syncthreads();
+        // column k above row k+1 becomes the zero part of v_k
+        for (int q = tid; q <= k; q += kBigBlock) S[(int64_t)k * ld + q] = T(0);
+        // (3) y = A22 v from the lower triangle, rows in blocks of 512: wave
+        // per column jj; the column's rows > jj add a*v[jj] to y (lane-held
+        // accumulators, 8 per lane), its rows >= jj give the column's dot
+        // product with v (kept by the owning wave). The waves' row partials
+        // are summed in a fixed order, so the result does not depend on
+        // scheduling.
+        for (int rb = 0; rb < n2; rb += 8 * kWave) {
+          constexpr int Q = 8;
+          constexpr int U = 2;
+          double yp[Q], vp[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int r = rb + lane + 64 * q;
+            yp[q] = 0.0;
+            vp[q] = r < n2 ? sv[r] : 0.0;
+          }
+          const T* A22 = S + (int64_t)(k + 1) * ld + (k + 1);
+          const int jend = (n2 < rb + 8 * kWave) ? n2 : rb + 8 * kWave;
+          for (int jb = U * wv; jb < jend; jb += U * kBigNW) {
+            double av[U][Q];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int jj = jb + u;
+              const T* col = A22 + (int64_t)jj * ld;
+#pragma unroll
+              for (int q = 0; q < Q; ++q) {
+                const int r = rb + lane + 64 * q;
+                av[u][q] = (jj < jend && r >= jj && r < n2) ? (double)col[r] : 0.0;
+              }
+            }
+            double dot[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int jj = jb + u;
+              const double vj = jj < jend ? sv[jj] : 0.0;
+              double t = 0.0;
+#pragma unroll
+              for (int q = 0; q < Q; ++q) {
+                const int r = rb + lane + 64 * q;
+                t = fma(av[u][q], vp[q], t);
+                if (r > jj) yp[q] = fma(av[u][q], vj, yp[q]);
+              }
+              dot[u] = t;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+              for (int u = 0; u < U; ++u) dot[u] += __shfl_xor(dot[u], off, kWave);
+            }
+            if (lane == 0) {
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                const int jj = jb + u;
+                if (jj < jend) {
+                  // the first row block holding rows of column jj sets its dot
+                  if (jj >= rb) sdot[jj] = dot[u];
+                  else sdot[jj] += dot[u];
+                }
+              }
+            }
+          }
+          // waves 0..3 store their partials, waves 4..7 add theirs
+          if (wv < 4) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              const int r = rb + lane + 64 * q;
+              if (r < n2) spart[wv * a.max_m + r] = yp[q];
+            }
+          }
+          __syncthreads();
+          if (wv >= 4) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              const int r = rb + lane + 64 * q;
+              if (r < n2) spart[(wv - 4) * a.max_m + r] += yp[q];
+            }
+          }
+          __syncthreads();
+        }
+        for (int r = tid; r < n2; r += kBigBlock)
+          sy[r] = sdot[r] + spart[r] + spart[a.max_m + r] + spart[2 * a.max_m + r] + spart[3 * a.max_m + r];
+        __syncthreads();
+        // (4) y -= V (W^T v) + W (V^T v) over the panel's earlier vectors
+        if (i > 0) {
+          for (int c = wv; c < i; c += kBigNW) {
+            const T* vc = S + (int64_t)(k0 + c) * ld + (k + 1);
+            const T* wc = Wb + (int64_t)c * ld + (k + 1);
+            double p1 = 0.0, p2 = 0.0;
+#pragma unroll 1
+            for (int r = lane; r < n2; r += kWave) {
+              p1 = fma((double)wc[r], sv[r], p1);
+              p2 = fma((double)vc[r], sv[r], p2);
+            }
+            p1 = wave_sum(p1);
+            p2 = wave_sum(p2);
+            if (lane == 0) {
+              z1[c] = p1;
+              z2[c] = p2;
+            }
+          }
+          __syncthreads();
+          for (int r = tid; r < n2; r += kBigBlock) {
+            double acc = sy[r];
+#pragma unroll 1
+            for (int c = 0; c < i; ++c)
+              acc -= (double)S[(int64_t)(k0 + c) * ld + (k + 1 + r)] * z1[c] +
+                     (double)Wb[(int64_t)c * ld + (k + 1 + r)] * z2[c];
+            sy[r] = acc;
+          }
+          __syncthreads();
+        }
+        // (5) w = tau y - (tau/2)(tau y . v) v into column i of W
+        double pv = 0.0;
+        for (int r = tid; r < n2; r += kBigBlock) pv = fma(tk * sy[r], sv[r], pv);
+        const double Kc = 0.5 * tk * block_sum<kBigNW>(pv, red);
+        for (int r = tid; r < n2; r += kBigBlock)
+          Wb[(int64_t)i * ld + (k + 1 + r)] = (T)(tk * sy[r] - Kc * sv[r]);
+        __syncthreads();
+      }
+      // trailing update A22 -= V W^T + W V^T (lower tiles)
+      const int c0 = k0 + nbt;
+      const int M = m - c0;
+      if (M > 0) {
+        const T* V2 = S + (int64_t)k0 * ld + c0;
+        const T* W2 = Wb + c0;
+        T* C = S + (int64_t)c0 * ld + c0;
+        wg_gemm<T, kBigNW, false, true, true>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kBigNW, false, true, true>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
       }
     }
     if (tid == 0) {
@@ -158,17 +313,27 @@ __global__ __launch_bounds__(kBlock) void k_tridiagonalise(LargeArgs a) {
       e[m - 1] = T(0);
     }
     __syncthreads();
+    // the last two columns carry no reflector: zero them
+    for (int q = tid; q < 2 * m; q += kBigBlock) {
+      const int c = q < m ? m - 2 : m - 1;
+      const int r = q < m ? q : q - m;
+      if (c >= 0) S[(int64_t)c * ld + r] = T(0);
+    }
   }
 }
 
 // ------------------------------------------------------------- form Q1
-// Q1 = H_0 H_1 ... H_{m-3}; backward accumulation from the identity:
-// Q[k+1:, k+1:] -= tau_k v_k (v_k^T Q[k+1:, k+1:]).
+// Q1 = B_0 B_1 ... with B_t = I - V_t T_t V_t^T the compact-WY form of NB
+// consecutive reflectors (T_t upper triangular: T[c][c] = tau_c,
+// T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c]). Backward accumulation
+// from the identity: Q22 -= V (T (V^T Q22)) with Q22 = Q[k0+1:, k0+1:].
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_form_q1(LargeArgs a) {
+__global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  __shared__ double Gs[kNB * kNB], Ts[kNB * kNB];
+  const int tid = threadIdx.x;
+  T* gsm = (T*)dyn;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -176,59 +341,111 @@ __global__ __launch_bounds__(kBlock) void k_form_q1(LargeArgs a) {
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
-    const T* S = at<T>(a.S, a.off[it]);
+    const T* S = at<T>((const void*)a.S, a.off[it]);
     T* Q = at<T>(a.Q, a.qoff[it]);
+    T* Wm = at<T>(a.W, a.off[it]);
     const T* tau = at<T>((const void*)a.tau, a.voff[it]);
-    T* sv = (T*)dyn;
-    T* sy = sv + a.max_m;
     const int64_t tot = (int64_t)ld * ld;
-    for (int64_t q = tid; q < tot; q += kBlock) {
+    for (int64_t q = tid; q < tot; q += kBigBlock) {
       const int64_t c = q / ld, r = q - c * ld;
       Q[q] = (r == c && r < m) ? T(1) : T(0);
     }
     __syncthreads();
-    for (int k = m - 3; k >= 0; --k) {
-      const T tk = tau[k];
-      if (tk == T(0)) continue;
-      const int n2 = m - k - 1;
-      const T* v = S + (int64_t)k * ld + (k + 1);
-      for (int i = tid; i < n2; i += kBlock) sv[i] = v[i];
-      __syncthreads();
-      T* Q22 = Q + (int64_t)(k + 1) * ld + (k + 1);
-      // y_c = sum_i v_i Q22[i][c]: one wave per column, lanes over rows
-      for (int c = wv; c < n2; c += kNW) {
-        double part = 0.0;
-        for (int i = lane; i < n2; i += kWave) part += (double)sv[i] * (double)Q22[(int64_t)c * ld + i];
-        part = wave_sum(part);
-        if (lane == 0) sy[c] = (T)((double)tk * part);
-      }
-      __syncthreads();
-      for (int i = tid; i < n2; i += kBlock) {
-        const T vi = sv[i];
-        for (int c = 0; c < n2; ++c) {
-          T* q = Q22 + (int64_t)c * ld + i;
-          *q = *q - vi * sy[c];
+    const int nref = m - 2;
+    if (nref > 0) {
+      const int nblk = (nref + kNB - 1) / kNB;
+      for (int t = nblk - 1; t >= 0; --t) {
+        const int k0 = t * kNB;
+        const int nbt = (nref - k0) < kNB ? (nref - k0) : kNB;
+        const int n2 = m - k0 - 1;
+        const T* V = S + (int64_t)k0 * ld + (k0 + 1);
+        // Gram matrix of the block's vectors
+        for (int q = tid; q < nbt * nbt; q += kBigBlock) {
+          const int r = q / nbt, c = q - r * nbt;
+          double g = 0.0;
+          if (r <= c) {
+            const T* vr = V + (int64_t)r * ld;
+            const T* vc = V + (int64_t)c * ld;
+            for (int s = c; s < n2; ++s) g = fma((double)vr[s], (double)vc[s], g);
+          }
+          Gs[r * kNB + c] = g;
         }
+        __syncthreads();
+        if (tid < kWave) {
+          for (int c = 0; c < nbt; ++c) {
+            const double tc = (double)tau[k0 + c];
+            // T[r][c] for r < c: -tau_c sum_{s=r}^{c-1} T[r][s] G[s][c]
+            double v = 0.0;
+            if (tid < c) {
+              for (int s = tid; s < c; ++s) v = fma(Ts[tid * kNB + s], Gs[s * kNB + c], v);
+              v = -tc * v;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (tid < c) Ts[tid * kNB + c] = v;
+            if (tid == c) Ts[c * kNB + c] = tc;
+            if (tid > c && tid < kNB) Ts[tid * kNB + c] = 0.0;
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+        __syncthreads();
+        // Wm (nbt x n2, ld nbt) = V^T Q22
+        T* Q22 = Q + (int64_t)(k0 + 1) * ld + (k0 + 1);
+        wg_gemm<T, kBigNW, true, false>(nbt, n2, n2, T(1), V, ld, Q22, ld, T(0), Wm, nbt, gsm);
+        // Wm = T Wm, 64 columns at a time through LDS
+        for (int c0 = 0; c0 < n2; c0 += 64) {
+          const int nc = (n2 - c0) < 64 ? (n2 - c0) : 64;
+          for (int q = tid; q < nbt * nc; q += kBigBlock) {
+            const int c = q / nbt, r = q - c * nbt;
+            gsm[c * kNB + r] = Wm[(int64_t)(c0 + c) * nbt + r];
+          }
+          __syncthreads();
+          for (int q = tid; q < nbt * nc; q += kBigBlock) {
+            const int c = q / nbt, r = q - c * nbt;
+            double acc = 0.0;
+            for (int q2 = r; q2 < nbt; ++q2) acc = fma(Ts[r * kNB + q2], (double)gsm[c * kNB + q2], acc);
+            Wm[(int64_t)(c0 + c) * nbt + r] = (T)acc;
+          }
+          __syncthreads();
+        }
+        // Q22 -= V Wm
+        wg_gemm<T, kBigNW, false, false>(n2, n2, nbt, T(-1), V, ld, Wm, nbt, T(1), Q22, ld, gsm);
       }
-      __syncthreads();
     }
   }
 }
 
 // ---------------------------------------------------------- QL on T
-// One lane per submatrix. Implicit QL with a Wilkinson shift on the
-// unreduced block [l, mm]; each sweep runs i = mm-1 down to l and records
-// its rotations (c, s): columns (i, i+1) of Q become
-// (c q_i - s q_{i+1}, s q_i + c q_{i+1}). Sweep table entry: hi, lo, offset.
+__device__ __forceinline__ void store_pair(double* p, double c, double s) {
+  *(double2*)p = make_double2(c, s);
+}
+__device__ __forceinline__ void store_pair(float* p, float c, float s) {
+  *(float2*)p = make_float2(c, s);
+}
+
+// One lane per submatrix, P submatrices per wave, d and e in LDS (FP64).
+// Implicit QL with a Wilkinson shift on the unreduced block [l, mm]; each
+// sweep runs i = mm-1 down to l and records its rotations (c, s): columns
+// (i, i+1) of Q become (c q_i - s q_{i+1}, s q_i + c q_{i+1}).
+// Sweep table entry: hi, lo, offset of its first rotation.
 template <class T>
 __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
-  const int it = blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= a.n_items) return;
+  extern __shared__ double dyn[];
+  const int P = a.ql_items;
+  const int LDL = a.max_m + 1;
+  const int lane = threadIdx.x;
+  const int it = blockIdx.x * P + lane;
+  if (lane >= P || it >= a.n_items) return;
   if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) return;
   const int j = a.items[it];
   const int m = a.rowptr[j + 1] - a.rowptr[j];
-  T* d = at<T>(a.d, a.doff[it]);
-  T* e = at<T>(a.e, a.voff[it]);
+  double* d = dyn + (int64_t)lane * LDL;
+  double* e = dyn + (int64_t)(P + lane) * LDL;
+  T* dg = at<T>(a.d, a.doff[it]);
+  const T* eg = at<T>((const void*)a.e, a.voff[it]);
+  for (int k = 0; k < m; ++k) {
+    d[k] = (double)dg[k];
+    e[k] = (double)eg[k];
+  }
   T* rot = at<T>(a.rot, a.roff[it]);
   int32_t* sw = a.sweeps + a.swoff[it];
   const int64_t rot_cap = 2 * (int64_t)m * m + 64;
@@ -237,53 +454,79 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
   int64_t nrot = 0;
   int nsw = 0;
   int flags = 0;
-  e[m - 1] = T(0);
+  e[m - 1] = 0.0;
   for (int l = 0; l < m && !(flags & LF_UNCONV); ++l) {
     int iter = 0;
     for (;;) {
-      int mm = l;
-      for (; mm < m - 1; ++mm) {
-        const double dd = fabs((double)d[mm]) + fabs((double)d[mm + 1]);
-        if (fabs((double)e[mm]) <= eps * dd) break;
+      // first negligible off-diagonal at or after l, eight entries per step
+      int mm = m - 1;
+      for (int k8 = l; k8 < m - 1; k8 += 8) {
+        int hit = -1;
+#pragma unroll
+        for (int u = 7; u >= 0; --u) {
+          const int kk = k8 + u;
+          if (kk < m - 1 && fabs(e[kk]) <= eps * (fabs(d[kk]) + fabs(d[kk + 1]))) hit = kk;
+        }
+        if (hit >= 0) {
+          mm = hit;
+          break;
+        }
       }
       if (mm == l) break;
       if (++iter > 40 || nsw >= sw_cap || nrot + (mm - l) > rot_cap) {
         flags |= LF_UNCONV;
         break;
       }
-      double g = ((double)d[l + 1] - (double)d[l]) / (2.0 * (double)e[l]);
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
       double r = hypot(g, 1.0);
-      g = (double)d[mm] - (double)d[l] + (double)e[l] / (g + (g >= 0.0 ? r : -r));
+      g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
       double s = 1.0, c = 1.0, pp = 0.0;
       const int64_t base = nrot;
-      int i = mm - 1;
       bool early = false;
-      double di = (double)d[i], ei = (double)e[i];
-      for (; i >= l; --i) {
-        // prefetch the next pair while this rotation is formed
+      // d[i+1] of iteration i is the d[i] that iteration i+1 read (the sweep
+      // only writes d[i+2] before it), so it is carried in a register
+      double dnext = d[mm];
+      double di = d[mm - 1], ei = e[mm - 1];
+      for (int i = mm - 1; i >= l; --i) {
         double dn = 0.0, en = 0.0;
-        if (i > l) { dn = (double)d[i - 1]; en = (double)e[i - 1]; }
+        if (i > l) { dn = d[i - 1]; en = e[i - 1]; }
         const double f = s * ei;
         const double b = c * ei;
-        r = hypot(f, g);
-        e[i + 1] = (T)r;
+        // r = hypot(f, g) and 1/r from one reciprocal square root refined by
+        // two Newton steps; the scaled fallback guards against overflow
+        const double af = fabs(f), ag = fabs(g);
+        const double big = af > ag ? af : ag;
+        double rinv;
+        if (big > 1e150 || big < 1e-150) {
+          r = hypot(f, g);
+          rinv = r != 0.0 ? 1.0 / r : 0.0;
+        } else {
+          const double x2 = fma(f, f, g * g);
+          double y = __builtin_amdgcn_rsq(x2);
+          double hx = x2 * y;
+          y = fma(0.5 * y, fma(-hx, y, 1.0), y);
+          hx = x2 * y;
+          y = fma(0.5 * y, fma(-hx, y, 1.0), y);
+          rinv = y;
+          r = x2 * y;
+        }
+        e[i + 1] = r;
         if (r == 0.0) {
-          d[i + 1] = (T)((double)d[i + 1] - pp);
-          e[mm] = T(0);
+          d[i + 1] = dnext - pp;
+          e[mm] = 0.0;
           early = true;
           break;
         }
-        const double rinv = 1.0 / r;
         s = f * rinv;
         c = g * rinv;
-        g = (double)d[i + 1] - pp;
+        g = dnext - pp;
         r = (di - g) * s + 2.0 * c * b;
         pp = s * r;
-        d[i + 1] = (T)(g + pp);
+        d[i + 1] = g + pp;
         g = c * r - b;
-        rot[2 * nrot] = (T)c;
-        rot[2 * nrot + 1] = (T)s;
+        store_pair(rot + 2 * nrot, (T)c, (T)s);
         ++nrot;
+        dnext = di;
         di = dn;
         ei = en;
       }
@@ -295,9 +538,9 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
         ++nsw;
       }
       if (early) continue;
-      d[l] = (T)((double)d[l] - pp);
-      e[l] = (T)g;
-      e[mm] = T(0);
+      d[l] -= pp;
+      e[l] = g;
+      e[mm] = 0.0;
     }
   }
   a.nsweeps[it] = nsw;
@@ -306,9 +549,10 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
   // submatrix to the FP64 pass
   double lmin = INFINITY, lmax = -INFINITY;
   for (int k = 0; k < m; ++k) {
-    const double v = (double)d[k];
+    const double v = d[k];
     lmin = fmin(lmin, v);
     lmax = fmax(lmax, v);
+    dg[k] = (T)v;
   }
   if (!a.fp64) {
     if ((flags & LF_UNCONV) || !(lmin > 0.0) || lmax > a.kappa_max * lmin) flags = LF_FALLBACK;
@@ -320,24 +564,28 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
   if (flags & LF_NONPOS) atomicAdd((unsigned long long*)&a.status[ST_NONPOS], 1ull);
   if (a.fp64 && (flags & LF_UNCONV)) atomicAdd((unsigned long long*)&a.status[ST_UNCONV], 1ull);
   if (!a.fp64 && (flags & LF_FALLBACK)) atomicAdd((unsigned long long*)&a.status[ST_FALLBACK], 1ull);
+  atomicAdd((unsigned long long*)&a.status[ST_ROTWORK], (unsigned long long)(nrot * m));
 }
 
 // ------------------------------------------------------ apply rotations
 // Q <- Q * G_1 * G_2 * ... (all recorded rotations, in order). A batch of K
 // sweeps is applied in one pass over each row: at step t sweep s acts on
-// columns (P, P+1), P = H - t + 2s, which keeps the per-row window at 2K
-// values (slots 2s, 2s+1 for sweep s) in registers.
-template <class T, int K>
+// columns (P, P+1), P = H - t + 2s. The logical window slot i (column
+// H - t + i) lives in register (i - t) mod 2K, so nothing is shifted; the
+// step loop is unrolled over 2K steps per LDS table chunk. Inactive
+// (sweep, step) pairs are identity rotations in the table. Each thread
+// carries RPT rows, so every coefficient read from LDS serves RPT rows.
+template <class T, int K, int RPT>
 __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
+  constexpr int TS = 2 * K;
   __shared__ int s_item;
   __shared__ int s_hi[K], s_lo[K], s_off[K];
+  __shared__ T tab[TS][K][2];
   const int tid = threadIdx.x;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
-    const int fl = a.flags[it];
-    if (a.only_flagged && !(fl & LF_FALLBACK)) continue;
-    if (!a.only_flagged && !a.fp64 && (fl & LF_FALLBACK)) continue;  // redone in FP64
+    if (skip_item(a, it)) continue;
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
@@ -361,7 +609,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
       }
       __syncthreads();
       int H = -1, L = m;
-#pragma unroll
       for (int s = 0; s < K; ++s) {
         if (s_hi[s] >= 0) {
           H = s_hi[s] > H ? s_hi[s] : H;
@@ -370,29 +617,64 @@ __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
       }
       if (H < 0) continue;
       const int tend = H + 2 * K - 1 - L;
-      for (int r = tid; r < m; r += kBlock) {
-        T w[2 * K];
+      for (int rb = 0; rb < m; rb += kBlock * RPT) {
+        int row[RPT];
+        bool act[RPT];
+        T w[RPT][TS];
 #pragma unroll
-        for (int q = 0; q < 2 * K; ++q) w[q] = T(0);
-        w[1] = Q[(int64_t)(H + 1) * ld + r];
-        for (int t = 0; t <= tend; ++t) {
-          const int base = H - t;
-          if (base >= L) w[0] = Q[(int64_t)base * ld + r];
+        for (int u = 0; u < RPT; ++u) {
+          row[u] = rb + tid + u * kBlock;
+          act[u] = row[u] < m;
 #pragma unroll
-          for (int s = 0; s < K; ++s) {
-            const int P = base + 2 * s;
+          for (int q = 0; q < TS; ++q) w[u][q] = T(0);
+          // slot 1 at t = 0 is column H+1 -> register 1
+          if (act[u]) w[u][1] = Q[(int64_t)(H + 1) * ld + row[u]];
+        }
+        for (int t0 = 0; t0 <= tend; t0 += TS) {
+          __syncthreads();
+          for (int q = tid; q < TS * K; q += kBlock) {
+            const int ts = q / K, s = q - ts * K;
+            const int P = H - (t0 + ts) + 2 * s;
+            T c = T(1), sn = T(0);
             if (P >= s_lo[s] && P <= s_hi[s]) {
               const int64_t idx = (int64_t)s_off[s] + (s_hi[s] - P);
-              const T c = rot[2 * idx], sn = rot[2 * idx + 1];
-              const T x0 = w[2 * s], x1 = w[2 * s + 1];
-              w[2 * s + 1] = sn * x0 + c * x1;
-              w[2 * s] = c * x0 - sn * x1;
+              c = rot[2 * idx];
+              sn = rot[2 * idx + 1];
+            }
+            tab[ts][s][0] = c;
+            tab[ts][s][1] = sn;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int ts = 0; ts < TS; ++ts) {
+            const int t = t0 + ts;
+            if (t <= tend) {
+              const int base = H - t;
+              // register of logical slot i at this step: (i - ts) mod TS
+              if (base >= L) {
+#pragma unroll
+                for (int u = 0; u < RPT; ++u)
+                  if (act[u]) w[u][(TS - ts) % TS] = Q[(int64_t)base * ld + row[u]];
+              }
+#pragma unroll
+              for (int s = 0; s < K; ++s) {
+                const int p0 = (2 * s - ts + 2 * TS) % TS, p1 = (2 * s + 1 - ts + 2 * TS) % TS;
+                const T c = tab[ts][s][0], sn = tab[ts][s][1];
+#pragma unroll
+                for (int u = 0; u < RPT; ++u) {
+                  const T x0 = w[u][p0], x1 = w[u][p1];
+                  w[u][p1] = sn * x0 + c * x1;
+                  w[u][p0] = c * x0 - sn * x1;
+                }
+              }
+              const int pout = base + TS - 1;
+              if (pout <= H + 1 && pout >= L) {
+#pragma unroll
+                for (int u = 0; u < RPT; ++u)
+                  if (act[u]) Q[(int64_t)pout * ld + row[u]] = w[u][(TS - 1 - ts + TS) % TS];
+              }
             }
           }
-          const int pout = base + 2 * K - 1;
-          if (pout <= H + 1 && pout >= L) Q[(int64_t)pout * ld + r] = w[2 * K - 1];
-#pragma unroll
-          for (int q = 2 * K - 1; q > 0; --q) w[q] = w[q - 1];
         }
       }
     }
@@ -411,15 +693,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
+    if (skip_item(a, it)) continue;
     const int fl = a.flags[it];
-    if (a.only_flagged && !(fl & LF_FALLBACK)) continue;
-    if (!a.only_flagged && !a.fp64 && (fl & LF_FALLBACK)) continue;
     const int j = a.items[it];
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
     const int ld = a.ldm[it];
     const int c = a.cidx[j];
-    const T* Q = at<T>(a.Q, a.qoff[it]);
+    const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
     const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
     for (int q = tid; q < m; q += kBlock) wv[q] = inv_root_p((double)lam[q], a.p) * (double)Q[(int64_t)q * ld + c];
@@ -434,121 +715,69 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
 }
 
 // --------------------------------------------------------------- adjoint
-// C = A * B (NN) or A * B^T (NT), m x m, column-major, leading dim ld.
-// 256 threads, 64x64 output tiles, 4x4 per thread, K steps of 16.
-template <class T, bool NT>
-__device__ void block_gemm(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int m,
-                           int ld, T* As, T* Bs) {
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  for (int ti = 0; ti < m; ti += 64) {
-    for (int tj = 0; tj < m; tj += 64) {
-      T acc[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = T(0);
-      for (int kk = 0; kk < m; kk += 16) {
-        __syncthreads();
-        for (int q = tid; q < 16 * 64; q += kBlock) {
-          const int kq = q >> 6, iq = q & 63;
-          const int gi = ti + iq, gk = kk + kq;
-          As[kq * 64 + iq] = (gi < m && gk < m) ? A[(int64_t)gk * ld + gi] : T(0);
-          const int gj = tj + iq;
-          T bv = T(0);
-          if (gj < m && gk < m) bv = NT ? B[(int64_t)gk * ld + gj] : B[(int64_t)gj * ld + gk];
-          Bs[kq * 64 + iq] = bv;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kq = 0; kq < 16; ++kq) {
-          T av[4], bv[4];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) av[x] = As[kq * 64 + ty * 4 + x];
-#pragma unroll
-          for (int y = 0; y < 4; ++y) bv[y] = Bs[kq * 64 + tx * 4 + y];
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += av[x] * bv[y];
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int gi = ti + ty * 4 + x, gj = tj + tx * 4 + y;
-          if (gi < m && gj < m) C[(int64_t)gj * ld + gi] = acc[x][y];
-        }
-      }
-    }
-  }
-  __syncthreads();
-}
-
+// a = Q^T w, b = Q[c,:]^T, Ms = (G o (a b^T + b a^T))/2, T1 = Q Ms,
+// D = T1 Q^T (lower tiles; D is symmetric), then every stored pair
+// (R[k], R[l]) at position q receives D[max(k,l)][min(k,l)].
 template <class T, class VT>
-__global__ __launch_bounds__(kBlock) void k_adjoint(LargeArgs a) {
+__global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  // dynamic LDS: R (max_m ints, padded to doubles), w, av, bv, alv (max_m doubles each),
-  // then two 16x64 GEMM staging tiles of T
   int* R = (int*)dyn;
   double* w = dyn + (a.max_m + 1) / 2 + 1;
   double* av = w + a.max_m;
   double* bv = av + a.max_m;
   double* alv = bv + a.max_m;
-  T* As = (T*)(alv + a.max_m);
-  T* Bs = As + 16 * 64;
+  T* gsm = (T*)(alv + a.max_m);
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
+    if (skip_item(a, it)) continue;
     const int fl = a.flags[it];
-    if (a.only_flagged && !(fl & LF_FALLBACK)) continue;
-    if (!a.only_flagged && !a.fp64 && (fl & LF_FALLBACK)) continue;
     const int j = a.items[it];
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
     const int ld = a.ldm[it];
     const int c = a.cidx[j];
-    const T* Q = at<T>(a.Q, a.qoff[it]);
+    const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     T* Ms = at<T>(a.S, a.off[it]);
     T* T1 = at<T>(a.W, a.off[it]);
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
     const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
     const VT* gx = (const VT*)a.gx + a0;
-    for (int i = tid; i < m; i += kBlock) {
+    for (int i = tid; i < m; i += kBigBlock) {
       R[i] = a.colind[a0 + i];
       w[i] = (double)gx[i];
       bv[i] = (double)Q[(int64_t)i * ld + c];
       alv[i] = root_p((double)lam[i], a.p);
     }
     __syncthreads();
-    // a = Q^T w: one wave per column p
-    for (int pc = wv; pc < m; pc += kNW) {
+    for (int pc = wv; pc < m; pc += kBigNW) {
       double part = 0.0;
       for (int r = lane; r < m; r += kWave) part = fma((double)Q[(int64_t)pc * ld + r], w[r], part);
       part = wave_sum(part);
       if (lane == 0) av[pc] = part;
     }
     __syncthreads();
-    // Ms[p][l] = (G o (a b^T + b a^T))/2
-    for (int l = wv; l < m; l += kNW) {
+    for (int l = wv; l < m; l += kBigNW) {
       for (int pr = lane; pr < m; pr += kWave) {
         const double g = divdiff(alv[pr], alv[l], a.p);
         Ms[(int64_t)l * ld + pr] = (T)(0.5 * g * (av[pr] * bv[l] + av[l] * bv[pr]));
       }
     }
     __syncthreads();
-    block_gemm<T, false>(Q, Ms, T1, m, ld, As, Bs);   // T1 = Q Ms
-    block_gemm<T, true>(T1, Q, Ms, m, ld, As, Bs);    // D = T1 Q^T (into the Ms slab)
+    wg_gemm<T, kBigNW, false, false>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
+    wg_gemm<T, kBigNW, false, true, true>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
     VT* ga = (VT*)a.ga;
-    for (int k = wv; k < m; k += kNW) {
+    for (int k = wv; k < m; k += kBigNW) {
       const int r = R[k];
       const int s0 = a.rowptr[r], s1 = a.rowptr[r + 1];
       for (int q = s0 + lane; q < s1; q += kWave) {
         const int l = find_sorted(R, m, a.colind[q]);
-        if (l >= 0) atomicAdd(&ga[q], bad ? (VT)NAN : (VT)Ms[(int64_t)l * ld + k]);
+        if (l >= 0) {
+          const int hi = l > k ? l : k, lo = l > k ? k : l;
+          atomicAdd(&ga[q], bad ? (VT)NAN : (VT)Ms[(int64_t)lo * ld + hi]);
+        }
       }
     }
   }
@@ -579,47 +808,67 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T>
+static void launch_tridiag_t(const LargeArgs& a, hipStream_t s) {
+  const size_t lds = vec_lds(a, 7, 8) + gemm_lds_elems<kBigNW>() * sizeof(T);
+  hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kBigBlock), lds, s, a);
+}
+
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  if (a.fp64)
-    hipLaunchKernelGGL(k_tridiagonalise<double>, dim3(a.grid), dim3(kBlock), vec_lds(a, 2, 8), s, a);
-  else
-    hipLaunchKernelGGL(k_tridiagonalise<float>, dim3(a.grid), dim3(kBlock), vec_lds(a, 2, 4), s, a);
+  if (a.fp64) launch_tridiag_t<double>(a, s);
+  else launch_tridiag_t<float>(a, s);
   return hipGetLastError();
 }
 
 hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.fp64)
-    hipLaunchKernelGGL(k_form_q1<double>, dim3(a.grid), dim3(kBlock), vec_lds(a, 2, 8), s, a);
+    hipLaunchKernelGGL(k_form_q1<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
   else
-    hipLaunchKernelGGL(k_form_q1<float>, dim3(a.grid), dim3(kBlock), vec_lds(a, 2, 4), s, a);
+    hipLaunchKernelGGL(k_form_q1<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_tridiag_ql(const LargeArgs& a, hipStream_t s) {
-  if (a.n_items <= 0) return hipSuccess;
-  const int grid = (a.n_items + 63) / 64;
+int ql_items_per_wave(int max_m, int lds_limit, int blocks_per_cu) {
+  // d and e of P submatrices in LDS (FP64), the device's LDS shared by
+  // blocks_per_cu blocks
+  const int64_t budget = ((int64_t)(lds_limit > 0 ? lds_limit : 65536) - 4096) / blocks_per_cu;
+  int p = (int)(budget / (16 * (int64_t)(max_m + 1)));
+  if (p > 64) p = 64;
+  if (p < 1) p = 1;
+  return p;
+}
+
+hipError_t launch_tridiag_ql(const LargeArgs& a0, hipStream_t s) {
+  if (a0.n_items <= 0) return hipSuccess;
+  LargeArgs a = a0;
+  a.ql_items = ql_items_per_wave(a.max_m, a.lds_limit, a.ql_bpc > 0 ? a.ql_bpc : 2);
+  const int grid = (a.n_items + a.ql_items - 1) / a.ql_items;
+  const size_t lds = (size_t)2 * a.ql_items * (a.max_m + 1) * sizeof(double);
   if (a.fp64)
-    hipLaunchKernelGGL(k_tridiag_ql<double>, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_tridiag_ql<double>, dim3(grid), dim3(64), lds, s, a);
   else
-    hipLaunchKernelGGL(k_tridiag_ql<float>, dim3(grid), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_tridiag_ql<float>, dim3(grid), dim3(64), lds, s, a);
   return hipGetLastError();
+}
+
+template <class T>
+static void launch_rot_t(const LargeArgs& a, hipStream_t s) {
+  const bool two = a.max_m > kBlock;
+  if (a.rot_batch >= 16) {
+    if (two) hipLaunchKernelGGL((k_apply_rotations<T, 16, 2>), dim3(a.grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_apply_rotations<T, 16, 1>), dim3(a.grid), dim3(kBlock), 0, s, a);
+  } else {
+    if (two) hipLaunchKernelGGL((k_apply_rotations<T, 8, 2>), dim3(a.grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_apply_rotations<T, 8, 1>), dim3(a.grid), dim3(kBlock), 0, s, a);
+  }
 }
 
 hipError_t launch_apply_rotations(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  if (a.fp64) {
-    if (a.rot_batch >= 16)
-      hipLaunchKernelGGL((k_apply_rotations<double, 16>), dim3(a.grid), dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_apply_rotations<double, 8>), dim3(a.grid), dim3(kBlock), 0, s, a);
-  } else {
-    if (a.rot_batch >= 16)
-      hipLaunchKernelGGL((k_apply_rotations<float, 16>), dim3(a.grid), dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_apply_rotations<float, 8>), dim3(a.grid), dim3(kBlock), 0, s, a);
-  }
+  if (a.fp64) launch_rot_t<double>(a, s);
+  else launch_rot_t<float>(a, s);
   return hipGetLastError();
 }
 
@@ -640,11 +889,11 @@ hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   const size_t base = ((size_t)(a.max_m + 1) / 2 + 1) * 8 + vec_lds(a, 4, 8);
   if (a.fp64) {
-    const size_t lds = base + 2 * 16 * 64 * sizeof(double);
-    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<double, VT>), dim3(a.grid), dim3(kBlock), lds, s, a));
+    const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(double);
+    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<double, VT>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
   } else {
-    const size_t lds = base + 2 * 16 * 64 * sizeof(float);
-    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<float, VT>), dim3(a.grid), dim3(kBlock), lds, s, a));
+    const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(float);
+    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<float, VT>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
   }
   return hipGetLastError();
 }

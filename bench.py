@@ -36,15 +36,23 @@ def flops_model(m):
     return float(((10.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
 
 
-def phase_flops(m, phase):
-    m = m.astype("float64")
+def phase_work(m, phase, rotwork):
+    """Algorithmic work of one launch of a phase over all large-order
+    submatrices: (amount, unit, bound)."""
+    m = m[m > 64].astype("float64")
     if phase == "tridiagonalise":
-        return float((4.0 / 3.0) * (m ** 3).sum())
+        return float((4.0 / 3.0) * (m ** 3).sum()), "flop", "alu"
     if phase == "form-q1":
-        return float((4.0 / 3.0) * (m ** 3).sum())
+        return float((4.0 / 3.0) * (m ** 3).sum()), "flop", "mfma"
+    if phase == "apply-rotations":
+        return 6.0 * float(rotwork), "flop", "alu"
     if phase == "adjoint":
-        return float(4.0 * (m ** 3).sum())
-    return None
+        return float(4.0 * (m ** 3).sum()), "flop", "mfma"
+    if phase == "gather":
+        return float(12.0 * (m ** 2).sum()), "byte", "hbm"
+    if phase == "apply-column":
+        return float(3.0 * (m ** 2).sum()), "flop", "alu"
+    return None, None, None
 
 
 # ------------------------------------------------------------- cpu baseline
@@ -109,6 +117,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -145,6 +155,14 @@ def main():
     def step():
         sm.invroot_fwd(rp, ci, va, args.p, prec, saved, out=x)
         sm.invroot_bwd(rp, ci, va, gx, args.p, prec, saved, out=ga)
+
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: 1 GiB read + 1 GiB written")
 
     for i in range(args.warmup):
         step()
@@ -189,24 +207,39 @@ def main():
 
     if not args.no_phases:
         ph = sm.time_phases(rp, ci, va, args.p, prec, grad_x=gx)
-        out["phases_ms"] = {k: round(v[0], 3) for k, v in ph.items() if v[1]}
-        dom = max((k for k in ph if ph[k][1]), key=lambda k: ph[k][0])
-        dom_ms = ph[dom][0] / max(ph[dom][1], 1)
-        fl = phase_flops(m, dom)
-        if fl is not None:
-            achieved = fl / (dom_ms / 1e3) / 1e12
-            out["roofline"] = {"kernel": dom, "bound": "alu", "achieved": achieved,
-                               "peak": FP64_VALU_PEAK, "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK,
-                               "traffic": None, "launch_ms": dom_ms}
+        counters = _lib.submat_query_counters(torch.cuda.current_stream().cuda_stream, 4)
+        rotwork = counters[3]
+        table = {}
+        for k, (ms, nl) in ph.items():
+            if not nl:
+                continue
+            per = ms / nl
+            amount, unit, bound = phase_work(m, k, rotwork)
+            row = {"ms_per_launch": round(per, 3), "launches": nl}
+            if amount is not None:
+                rate = amount / (per / 1e3)
+                row["achieved"] = rate / (1e9 if unit == "byte" else 1e12)
+                row["unit"] = "GB/s" if unit == "byte" else "TFLOP/s"
+                row["bound"] = bound
+            table[k] = row
+        out["phases"] = table
+        dom = max(table, key=lambda k: table[k]["ms_per_launch"])
+        d = table[dom]
+        if "achieved" in d:
+            peak = HBM_PEAK_GBS if d["unit"] == "GB/s" else FP64_PEAK_TFLOPS
+            out["roofline"] = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": peak,
+                               "unit": d["unit"], "frac": d["achieved"] / peak, "traffic": None,
+                               "launch_ms": d["ms_per_launch"]}
         else:
-            out["roofline"] = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_VALU_PEAK,
-                               "unit": "TFLOP/s", "frac": None, "traffic": None, "launch_ms": dom_ms}
-        log(f"phases {out['phases_ms']}")
+            out["roofline"] = {"kernel": dom, "bound": "latency", "achieved": None, "peak": None,
+                               "unit": None, "frac": None, "traffic": None, "launch_ms": d["ms_per_launch"]}
+        out["rotation_row_updates"] = rotwork
+        log(f"phases {table}")
 
     if not args.no_plain:
-        # the per-column comparison path on the same recipe at 64 atoms
-        # (n = 832, submatrix orders ~390 like the full workload)
-        small = G.overlap_matrix(n_atoms=64, nbf=13, rcut=4.14, kappa=100.0, seed=G.BASE_SEED + 2)
+        # the per-column comparison path on the same recipe at 32 atoms
+        # (n = 416, submatrix orders ~400 like the full workload)
+        small = G.overlap_matrix(n_atoms=32, nbf=13, rcut=4.14, kappa=100.0, seed=G.BASE_SEED + 2)
         srp = torch.from_numpy(small.rowptr).cuda()
         sci = torch.from_numpy(small.colind).cuda()
         sva = torch.from_numpy(small.vals).cuda()
@@ -220,7 +253,7 @@ def main():
         plain_rate = small.n / (time.perf_counter() - tp)
         ms_ = small.row_sizes().astype(float)
         out["plain_f64_path"] = {"value": plain_rate, "unit": "submatrices/s",
-                                 "workload": f"same recipe, 64 atoms (n={small.n}, m mean {ms_.mean():.0f})",
+                                 "workload": f"same recipe, 32 atoms (n={small.n}, m mean {ms_.mean():.0f})",
                                  "speedup_batched_vs_plain": value / plain_rate}
         log(f"plain path {plain_rate:.1f} submatrices/s")
 

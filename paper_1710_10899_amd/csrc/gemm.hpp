@@ -44,24 +44,55 @@ template <> struct Mfma<float> {
 constexpr int kGemmBM = 64;
 constexpr int kGemmBK = 16;
 
+// LDS layout of a staged operand tile follows its order in global memory,
+// so that both the store (consecutive threads, consecutive addresses) and
+// the MFMA operand read are free of bank conflicts:
+//  * contiguous along i (or j): k-major rows [BK][W + 16]; the stride is 16
+//    doubles off a multiple of the bank width, so the four k-rows one MFMA
+//    read touches fall in different bank halves;
+//  * contiguous along k: k-minor rows [W][BK + 1]; the odd stride spreads the
+//    16 rows of one MFMA read over distinct banks.
+constexpr int kGemmPad = 16;
+template <int W> constexpr int tile_elems_major() { return kGemmBK * (W + kGemmPad); }
+template <int W> constexpr int tile_elems_minor() { return W * (kGemmBK + 1); }
+template <int W> constexpr int tile_elems() {
+  return tile_elems_major<W>() > tile_elems_minor<W>() ? tile_elems_major<W>() : tile_elems_minor<W>();
+}
 // LDS elements of T needed by wg_gemm with NW waves.
-template <int NW> constexpr int gemm_lds_elems() { return kGemmBK * kGemmBM + kGemmBK * 16 * NW; }
+template <int NW> constexpr int gemm_lds_elems() { return tile_elems<kGemmBM>() + tile_elems<16 * NW>(); }
 
 // TA: op(A) = A^T (A stored K x M); TB: op(B) = B^T (B stored N x K).
 // LOWER: tiles lying entirely above the diagonal of C are skipped (for
 // symmetric results kept in the lower triangle).
 // Must be called by every thread of the workgroup (contains barriers).
-template <class T, int NW, bool TA, bool TB, bool LOWER = false>
+// PREFETCH: the next k-tile is fetched into registers while the current one
+// is multiplied (costs 6-8 registers; off where registers are scarce).
+template <class T, int NW, bool TA, bool TB, bool LOWER = false, bool PREFETCH = true>
 __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, int lda,
                         const T* __restrict__ B, int ldb, T beta, T* __restrict__ C, int ldc, T* smem) {
   constexpr int BM = kGemmBM, BK = kGemmBK, BN = 16 * NW, NT = NW * kWave;
+  constexpr int AL = BM * BK / NT, BL = BN * BK / NT;  // tile elements per thread
   typedef typename Mfma<T>::acc_t acc_t;
-  T* As = smem;            // [BK][BM]
-  T* Bs = smem + BK * BM;  // [BK][BN]
+  // A tile: k-major unless A is transposed (then contiguous along k);
+  // B tile: k-major if B is transposed (contiguous along j), else k-minor.
+  constexpr int SA = TA ? BK + 1 : BM + kGemmPad;
+  constexpr int SB = TB ? BN + kGemmPad : BK + 1;
+  T* As = smem;
+  T* Bs = smem + tile_elems<BM>();
+  auto a_at = [&](int kq, int iq) -> T& { return TA ? As[iq * SA + kq] : As[kq * SA + iq]; };
+  auto b_at = [&](int kq, int jq) -> T& { return TB ? Bs[kq * SB + jq] : Bs[jq * SB + kq]; };
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int wr = wv & 1, wc = wv >> 1;
   const int li = lane & 15, lk = lane >> 4;
+  // element q of a tile -> (k, i) position; storage order follows the
+  // contiguous direction of the operand in memory
+  auto a_pos = [&](int q, int& kq, int& iq) {
+    if (TA) { iq = q / BK; kq = q - iq * BK; } else { kq = q / BM; iq = q - kq * BM; }
+  };
+  auto b_pos = [&](int q, int& kq, int& jq) {
+    if (TB) { kq = q / BN; jq = q - kq * BN; } else { jq = q / BK; kq = q - jq * BK; }
+  };
   for (int i0 = 0; i0 < M; i0 += BM) {
     for (int j0 = 0; j0 < N; j0 += BN) {
       if (LOWER && j0 >= i0 + BM) continue;
@@ -70,36 +101,50 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-      for (int k0 = 0; k0 < K; k0 += BK) {
-        __syncthreads();
-        // A tile: op(A)[i0 .. i0+BM) x [k0 .. k0+BK)
-        for (int q = tid; q < BM * BK; q += NT) {
+      // the next k-tile is fetched into registers while the current one is
+      // multiplied from LDS
+      T ra[AL], rb[BL];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AL; ++e) {
           int kq, iq;
-          if (TA) { iq = q / BK; kq = q - iq * BK; }   // contiguous along k in storage
-          else { kq = q / BM; iq = q - kq * BM; }      // contiguous along i in storage
+          a_pos(tid + e * NT, kq, iq);
           const int gi = i0 + iq, gk = k0 + kq;
-          T v = T(0);
-          if (gi < M && gk < K) v = TA ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi];
-          As[kq * BM + iq] = v;
+          ra[e] = (gi < M && gk < K) ? (TA ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi]) : T(0);
         }
-        // B tile: op(B)[k0 .. k0+BK) x [j0 .. j0+BN)
-        for (int q = tid; q < BN * BK; q += NT) {
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
           int kq, jq;
-          if (TB) { kq = q / BN; jq = q - kq * BN; }   // contiguous along j in storage
-          else { jq = q / BK; kq = q - jq * BK; }      // contiguous along k in storage
+          b_pos(tid + e * NT, kq, jq);
           const int gj = j0 + jq, gk = k0 + kq;
-          T v = T(0);
-          if (gj < N && gk < K) v = TB ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk];
-          Bs[kq * BN + jq] = v;
+          rb[e] = (gj < N && gk < K) ? (TB ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk]) : T(0);
+        }
+      };
+      if (PREFETCH) fetch(0);
+      for (int k0 = 0; k0 < K; k0 += BK) {
+        if (!PREFETCH) fetch(k0);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < AL; ++e) {
+          int kq, iq;
+          a_pos(tid + e * NT, kq, iq);
+          a_at(kq, iq) = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+          int kq, jq;
+          b_pos(tid + e * NT, kq, jq);
+          b_at(kq, jq) = rb[e];
         }
         __syncthreads();
+        if (PREFETCH && k0 + BK < K) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
           T av[2], bv[2];
 #pragma unroll
-          for (int a = 0; a < 2; ++a) av[a] = As[(kk + lk) * BM + wr * 32 + a * 16 + li];
+          for (int a = 0; a < 2; ++a) av[a] = a_at(kk + lk, wr * 32 + a * 16 + li);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) bv[b] = Bs[(kk + lk) * BN + wc * 32 + b * 16 + li];
+          for (int b = 0; b < 2; ++b) bv[b] = b_at(kk + lk, wc * 32 + b * 16 + li);
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll

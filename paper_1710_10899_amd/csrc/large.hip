@@ -3,8 +3,8 @@
 //
 //   gather      S_j from CSR into an HBM slab (Section 3.1), symmetrised
 //   tridiag     blocked Householder reduction S = Q1 T Q1^T (lower form): per
-//               panel of NB columns a lower-triangle symv per column, and one
-//               rank-2*NB trailing update on MFMA (lower tiles only)
+//               panel of NB columns a row-parallel symv per column, and one
+//               rank-2*NB trailing update on MFMA
 //   form_q1     Q1 accumulated explicitly from compact-WY blocks of NB
 //               reflectors, products on MFMA
 //   ql          implicit QL with Wilkinson shifts on T (d, e in LDS); the
@@ -20,9 +20,8 @@
 //               stored pairs
 //
 // Slabs are column-major with leading dimension ldm (the order rounded up
-// to a multiple of 16). After the reduction only the lower triangle of the
-// working matrix is meaningful, and column k of the S slab holds the full
-// Householder vector v_k (zeros above row k+1, 1 at row k+1).
+// to a multiple of 16). After the reduction column k of the S slab holds the
+// full Householder vector v_k (zeros above row k+1, 1 at row k+1).
 #include <math.h>
 
 #include "common.hpp"
@@ -96,8 +95,9 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
 // earlier vectors (A[k:, k] -= V W[k,:]^T + W V[k,:]^T), its reflector
 // (v, tau, beta) is formed, and w = tau (A22 v - V (W^T v) - W (V^T v)),
 // w -= (tau/2)(w.v) v, where A22 is the trailing matrix as it stood at the
-// start of the panel (lower triangle only). After the panel,
-// A22 -= V W^T + W V^T on MFMA.
+// start of the panel. After the panel, A22 -= V W^T + W V^T on MFMA. Both
+// triangles of the trailing matrix are kept, so the symv streams whole
+// columns with one multiply-add per element and no cross-lane reduction.
 // Outputs: d[0..m), e[0..m-1), tau[0..m-2) and v_k in column k of S.
 template <class T>
 __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
@@ -108,9 +108,7 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   double* sv = dyn;                     // v (max_m)
   double* sy = dyn + a.max_m;           // y = A22 v (max_m)
-  double* sdot = dyn + 2 * a.max_m;     // column dots of the symv (max_m)
-  double* spart = dyn + 3 * a.max_m;    // row partials of waves 0..3 (4 x max_m)
-  T* gsm = (T*)(dyn + 7 * a.max_m);
+  T* gsm = (T*)(dyn + 2 * a.max_m);
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -173,87 +171,35 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         __syncthreads();
         // column k above row k+1 becomes the zero part of v_k
         for (int q = tid; q <= k; q += kBigBlock) S[(int64_t)k * ld + q] = T(0);
-        // (3) y = A22 v from the lower triangle, rows in blocks of 512: wave
-        // per column jj; the column's rows > jj add a*v[jj] to y (lane-held
-        // accumulators, 8 per lane), its rows >= jj give the column's dot
-        // product with v (kept by the owning wave). The waves' row partials
-        // are summed in a fixed order, so the result does not depend on
-        // scheduling.
-        for (int rb = 0; rb < n2; rb += 8 * kWave) {
-          constexpr int Q = 8;
-          constexpr int U = 2;
-          double yp[Q], vp[Q];
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            const int r = rb + lane + 64 * q;
-            yp[q] = 0.0;
-            vp[q] = r < n2 ? sv[r] : 0.0;
-          }
+        // (3) y = A22 v, A22 = the trailing matrix as it stood at the start
+        // of the panel (both triangles kept): one thread per row, columns
+        // streamed with a uniform base address, four partial sums.
+        {
           const T* A22 = S + (int64_t)(k + 1) * ld + (k + 1);
-          const int jend = (n2 < rb + 8 * kWave) ? n2 : rb + 8 * kWave;
-          for (int jb = U * wv; jb < jend; jb += U * kBigNW) {
-            double av[U][Q];
+          for (int r0 = 0; r0 < n2; r0 += kBigBlock) {
+            const int r = r0 + tid;
+            if (r < n2) {
+              double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+              int jj = 0;
+              // eight column loads in flight per thread
+              for (; jj + 8 <= n2; jj += 8) {
+                double av[8];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int jj = jb + u;
-              const T* col = A22 + (int64_t)jj * ld;
-#pragma unroll
-              for (int q = 0; q < Q; ++q) {
-                const int r = rb + lane + 64 * q;
-                av[u][q] = (jj < jend && r >= jj && r < n2) ? (double)col[r] : 0.0;
+                for (int u = 0; u < 8; ++u) av[u] = (double)(A22 + (int64_t)(jj + u) * ld)[r];
+                acc0 = fma(av[0], sv[jj], acc0);
+                acc1 = fma(av[1], sv[jj + 1], acc1);
+                acc2 = fma(av[2], sv[jj + 2], acc2);
+                acc3 = fma(av[3], sv[jj + 3], acc3);
+                acc0 = fma(av[4], sv[jj + 4], acc0);
+                acc1 = fma(av[5], sv[jj + 5], acc1);
+                acc2 = fma(av[6], sv[jj + 6], acc2);
+                acc3 = fma(av[7], sv[jj + 7], acc3);
               }
-            }
-            double dot[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const int jj = jb + u;
-              const double vj = jj < jend ? sv[jj] : 0.0;
-              double t = 0.0;
-#pragma unroll
-              for (int q = 0; q < Q; ++q) {
-                const int r = rb + lane + 64 * q;
-                t = fma(av[u][q], vp[q], t);
-                if (r > jj) yp[q] = fma(av[u][q], vj, yp[q]);
-              }
-              dot[u] = t;
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-              for (int u = 0; u < U; ++u) dot[u] += __shfl_xor(dot[u], off, kWave);
-            }
-            if (lane == 0) {
-#pragma unroll
-              for (int u = 0; u < U; ++u) {
-                const int jj = jb + u;
-                if (jj < jend) {
-                  // the first row block holding rows of column jj sets its dot
-                  if (jj >= rb) sdot[jj] = dot[u];
-                  else sdot[jj] += dot[u];
-                }
-              }
+              for (; jj < n2; ++jj) acc0 = fma((double)(A22 + (int64_t)jj * ld)[r], sv[jj], acc0);
+              sy[r] = (acc0 + acc1) + (acc2 + acc3);
             }
           }
-          // waves 0..3 store their partials, waves 4..7 add theirs
-          if (wv < 4) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-              const int r = rb + lane + 64 * q;
-              if (r < n2) spart[wv * a.max_m + r] = yp[q];
-            }
-          }
-          __syncthreads();
-          if (wv >= 4) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-              const int r = rb + lane + 64 * q;
-              if (r < n2) spart[(wv - 4) * a.max_m + r] += yp[q];
-            }
-          }
-          __syncthreads();
         }
-        for (int r = tid; r < n2; r += kBigBlock)
-          sy[r] = sdot[r] + spart[r] + spart[a.max_m + r] + spart[2 * a.max_m + r] + spart[3 * a.max_m + r];
         __syncthreads();
         // (4) y -= V (W^T v) + W (V^T v) over the panel's earlier vectors
         if (i > 0) {
@@ -299,8 +245,8 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         const T* V2 = S + (int64_t)k0 * ld + c0;
         const T* W2 = Wb + c0;
         T* C = S + (int64_t)c0 * ld + c0;
-        wg_gemm<T, kBigNW, false, true, true>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
-        wg_gemm<T, kBigNW, false, true, true>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kBigNW, false, true, false, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kBigNW, false, true, false, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
       }
     }
     if (tid == 0) {
@@ -487,9 +433,12 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
       // only writes d[i+2] before it), so it is carried in a register
       double dnext = d[mm];
       double di = d[mm - 1], ei = e[mm - 1];
+      // d[i-1], e[i-1] were read one iteration earlier; d[i-2], e[i-2] are
+      // requested now, so no LDS read is waited on in the rotation chain
+      double dn = mm - 2 >= l ? d[mm - 2] : 0.0, en = mm - 2 >= l ? e[mm - 2] : 0.0;
       for (int i = mm - 1; i >= l; --i) {
-        double dn = 0.0, en = 0.0;
-        if (i > l) { dn = d[i - 1]; en = e[i - 1]; }
+        double dnn = 0.0, enn = 0.0;
+        if (i - 2 >= l) { dnn = d[i - 2]; enn = e[i - 2]; }
         const double f = s * ei;
         const double b = c * ei;
         // r = hypot(f, g) and 1/r from one reciprocal square root refined by
@@ -529,6 +478,8 @@ __global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
         dnext = di;
         di = dn;
         ei = en;
+        dn = dnn;
+        en = enn;
       }
       const int cnt = (int)(nrot - base);
       if (cnt > 0) {
@@ -621,6 +572,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
         int row[RPT];
         bool act[RPT];
         T w[RPT][TS];
+        // columns are loaded PF steps before they enter the window
+        constexpr int PF = 8;
+        T pf[RPT][PF];
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
           row[u] = rb + tid + u * kBlock;
@@ -629,6 +583,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
           for (int q = 0; q < TS; ++q) w[u][q] = T(0);
           // slot 1 at t = 0 is column H+1 -> register 1
           if (act[u]) w[u][1] = Q[(int64_t)(H + 1) * ld + row[u]];
+#pragma unroll
+          for (int q = 0; q < PF; ++q) {
+            const int col = H - q;
+            pf[u][q] = (act[u] && col >= L) ? Q[(int64_t)col * ld + row[u]] : T(0);
+          }
         }
         for (int t0 = 0; t0 <= tend; t0 += TS) {
           __syncthreads();
@@ -650,11 +609,17 @@ __global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
             const int t = t0 + ts;
             if (t <= tend) {
               const int base = H - t;
-              // register of logical slot i at this step: (i - ts) mod TS
+              // register of logical slot i at this step: (i - ts) mod TS;
+              // the column entering now was prefetched into pf[ts % PF]
               if (base >= L) {
 #pragma unroll
+                for (int u = 0; u < RPT; ++u) w[u][(TS - ts) % TS] = pf[u][ts % PF];
+              }
+              const int cpf = base - PF;
+              if (cpf >= L) {
+#pragma unroll
                 for (int u = 0; u < RPT; ++u)
-                  if (act[u]) w[u][(TS - ts) % TS] = Q[(int64_t)base * ld + row[u]];
+                  if (act[u]) pf[u][ts % PF] = Q[(int64_t)cpf * ld + row[u]];
               }
 #pragma unroll
               for (int s = 0; s < K; ++s) {
@@ -810,7 +775,7 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
 
 template <class T>
 static void launch_tridiag_t(const LargeArgs& a, hipStream_t s) {
-  const size_t lds = vec_lds(a, 7, 8) + gemm_lds_elems<kBigNW>() * sizeof(T);
+  const size_t lds = vec_lds(a, 2, 8) + gemm_lds_elems<kBigNW>() * sizeof(T);
   hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kBigBlock), lds, s, a);
 }
 

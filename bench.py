@@ -24,6 +24,13 @@ FP64_VALU_PEAK = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK = 78.6       # unpacked FP32 VALU: same lane rate as FP64
 HBM_PEAK_GBS = 8000.0
 
+# library kernel (substring of its symbol) -> phase of submat_time_phases
+KERNEL_PHASE = {"k_small": "small-jacobi", "k_gather_large": "gather", "k_tridiagonalise": "tridiagonalise",
+                "k_form_q1": "form-q1", "k_tridiag_ql": "tridiagonal-ql", "k_apply_rotations": "apply-rotations",
+                "k_apply_column": "apply-column", "k_adjoint": "adjoint", "k_plan_pattern": "plan-reset"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+CSRC = os.path.join(ROOT, "paper_1710_10899_amd", "csrc")
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -53,6 +60,96 @@ def phase_work(m, phase, rotwork):
     if phase == "apply-column":
         return float(3.0 * (m ** 2).sum()), "flop", "alu"
     return None, None, None
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources; HBM counter figures taken for another
+    version of the kernels are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(phase: str):
+    """HBM bytes per launch (FETCH + WRITE, calibrated) of a phase's kernel
+    from the committed counter summary, or None when absent or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    k = t.get("phases", {}).get(phase)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
+def _phase_of(name: str):
+    for k, ph in KERNEL_PHASE.items():
+        if k in name:
+            return ph + ("/f32" if ("<float" in name or "IfE" in name) else "")
+    return None
+
+
+def summarise_profile(d: str, command: str) -> None:
+    """Turns one rocprofv3 kernel-trace run (kt_*) and two counter runs
+    (fetch_*: FETCH_SIZE, write_*: WRITE_SIZE, all --output-format csv) of
+    this benchmark, made with --copy-probe, into profiles/<workload>.md and
+    profiles/traffic.json. The 1 GiB probe copy calibrates the counters:
+    scale = bytes moved / bytes the counter reports for it."""
+    import csv
+    import collections
+    stats = {}
+    with open(os.path.join(d, "kt_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            stats[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]) / 1e6, float(r["Percentage"]))
+    ctr = {}
+    for tag, cname in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        per = collections.defaultdict(list)
+        with open(os.path.join(d, f"{tag}_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == cname:
+                    per[(r["Kernel_Name"], r["Dispatch_Id"])].append(float(r["Counter_Value"]))
+        byk = collections.defaultdict(list)
+        for (k, _), v in per.items():
+            byk[k].append(sum(v) * 1024.0)   # KiB -> bytes
+        probe = max((max(v) for k, v in byk.items() if _phase_of(k) is None), default=0.0)
+        scale = (1 << 30) / probe if probe > 0 else float("nan")
+        ctr[tag] = ({k: scale * sum(v) / len(v) for k, v in byk.items()}, scale)
+    sha = kernel_source_hash()
+    phases = {}
+    lines = ["# rocprofv3 summary: submatrix-method kernels, overlap workload n=6656 (512 atoms x 13), "
+             "forward + adjoint, FP64", "", "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` "
+             "first, output directory then passed to `python bench.py --summarise-profile DIR`):", "", "```",
+             command, "```", "",
+             f"Counter calibration (1 GiB device copy): FETCH_SIZE x{ctr['fetch'][1]:.3f}, "
+             f"WRITE_SIZE x{ctr['write'][1]:.3f}.", f"Kernel sources sha256: `{sha}`", "",
+             "| kernel | phase | calls | avg ms | % time | HBM read GB/launch | HBM write GB/launch | GB/s |",
+             "|---|---|---|---|---|---|---|---|"]
+    for name, (calls, ms, pct) in sorted(stats.items(), key=lambda kv: -kv[1][2]):
+        ph = _phase_of(name)
+        fb = ctr["fetch"][0].get(name)
+        wb = ctr["write"][0].get(name)
+        short = name.split("(")[0].replace("void ", "")[:60]
+        if fb is not None and wb is not None:
+            gbs = (fb + wb) / (ms / 1e3) / 1e9
+            lines.append(f"| `{short}` | {ph or '-'} | {calls} | {ms:.3f} | {pct:.2f} | {fb / 1e9:.2f} | "
+                         f"{wb / 1e9:.2f} | {gbs:.0f} |")
+            if ph is not None and "/f32" not in ph:
+                phases[ph] = {"kernel": short, "avg_ms": ms, "fetch_bytes": fb, "write_bytes": wb}
+        else:
+            lines.append(f"| `{short}` | {ph or '-'} | {calls} | {ms:.3f} | {pct:.2f} | - | - | - |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "overlap_n6656_fwd_adjoint_f64.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump({"source_sha256": sha, "command": command, "fetch_scale": ctr["fetch"][1],
+                   "write_scale": ctr["write"][1], "phases": phases}, fh, indent=1)
+    print("\n".join(lines))
 
 
 # ------------------------------------------------------------- cpu baseline
@@ -119,7 +216,13 @@ def main():
     ap.add_argument("--no-phases", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device-to-device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--summarise-profile", metavar="DIR",
+                    help="summarise rocprofv3 csv output of this benchmark into profiles/ and exit")
+    ap.add_argument("--profile-command", default="", help="command line recorded with --summarise-profile")
     args = ap.parse_args()
+    if args.summarise_profile:
+        summarise_profile(args.summarise_profile, args.profile_command)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(the multi-GPU sharding is a design only)"}))
@@ -228,11 +331,12 @@ def main():
         if "achieved" in d:
             peak = HBM_PEAK_GBS if d["unit"] == "GB/s" else FP64_PEAK_TFLOPS
             out["roofline"] = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": peak,
-                               "unit": d["unit"], "frac": d["achieved"] / peak, "traffic": None,
+                               "unit": d["unit"], "frac": d["achieved"] / peak, "traffic": measured_traffic(dom),
                                "launch_ms": d["ms_per_launch"]}
         else:
             out["roofline"] = {"kernel": dom, "bound": "latency", "achieved": None, "peak": None,
-                               "unit": None, "frac": None, "traffic": None, "launch_ms": d["ms_per_launch"]}
+                               "unit": None, "frac": None, "traffic": measured_traffic(dom),
+                               "launch_ms": d["ms_per_launch"]}
         out["rotation_row_updates"] = rotwork
         log(f"phases {table}")
 

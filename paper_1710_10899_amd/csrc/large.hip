@@ -89,15 +89,109 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
   }
 }
 
+// ------------------------------------------------------- symmetric matvec
+// y = A v for a symmetric n x n matrix given by its lower triangle (column
+// major, leading dimension ld), v and y in LDS, called by the whole
+// 512-thread workgroup. The columns are cut into strips of kStrip; wave w
+// takes strips w, 2*NW-1-w, 2*NW+w, ... (balanced over the triangle). For a
+// strip the lanes run down the rows r >= c0 in groups of 64; each lane loads
+// kStrip elements of its row (one coalesced column segment per load) and
+//   * adds sum_c A[r][c] v[c] to its wave's row partial spart[w][r];
+//   * accumulates A[r][c] v[r] (r > c) for each of the strip's columns,
+//     reduced across the wave at the end of the strip.
+// y = sum over waves of the partials, in a fixed order (deterministic).
+constexpr int kStrip = 8;
+
+// Column-dot reduction of a strip: 64 lanes each hold kStrip partials. Lane
+// l keeps the strip's columns in slots permuted by u -> u ^ p(l), with
+// p(l) = sum over halving steps h of h * bit(l, h * 64 / kStrip). Then each
+// halving step is the same for every lane, x[q] += x'[q + h] from the lane
+// across that bit, and after the steps slot 0 of lane l holds a partial of
+// column p(l) over the lanes that differ in the remaining low bits.
+__device__ __forceinline__ int strip_perm(int lane) {
+  int p = 0;
+#pragma unroll
+  for (int h = kStrip / 2; h >= 1; h >>= 1) p += (lane & (h * (kWave / kStrip))) ? h : 0;
+  return p;
+}
+__device__ __forceinline__ double wave_strip_sum(double (&x)[kStrip]) {
+#pragma unroll
+  for (int h = kStrip / 2; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int q = 0; q < h; ++q) x[q] += __shfl_xor(x[q + h], h * (kWave / kStrip));
+  }
+  double t = x[0];
+#pragma unroll
+  for (int bit = kWave / kStrip / 2; bit >= 1; bit >>= 1) t += __shfl_xor(t, bit);
+  return t;
+}
+
+template <class T>
+__device__ void symv_lower(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
+                           double* y, double* spart, int max_m) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int pl = strip_perm(lane);
+  double* my = spart + (int64_t)wv * max_m;
+  for (int r = lane; r < n; r += kWave) my[r] = 0.0;
+  const int nstrip = (n + kStrip - 1) / kStrip;
+  for (int t = 0;; ++t) {
+    const int s = t * kBigNW + ((t & 1) ? (kBigNW - 1 - wv) : wv);
+    if (s >= nstrip) break;
+    const int c0 = s * kStrip;
+    double vc[kStrip], cd[kStrip];
+    const T* col[kStrip];
+#pragma unroll
+    for (int u = 0; u < kStrip; ++u) {
+      const int c = c0 + (u ^ pl);
+      vc[u] = (c < n) ? v[c] : 0.0;
+      cd[u] = 0.0;
+      col[u] = A + (int64_t)(c < n ? c : c0) * ld;
+    }
+    for (int r = c0 + lane; r - lane < n; r += kWave) {
+      const bool in = r < n;
+      double av[kStrip];
+#pragma unroll
+      for (int u = 0; u < kStrip; ++u) av[u] = (in && c0 + (u ^ pl) < n) ? (double)col[u][r] : 0.0;
+      const double vr = in ? v[r] : 0.0;
+      double racc = 0.0;
+      if (r - lane >= c0 + kStrip) {  // the whole group lies below the diagonal block
+#pragma unroll
+        for (int u = 0; u < kStrip; ++u) {
+          racc = fma(av[u], vc[u], racc);
+          cd[u] = fma(av[u], vr, cd[u]);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kStrip; ++u) {
+          const int c = c0 + (u ^ pl);
+          const double a_ = (r >= c) ? av[u] : 0.0;
+          racc = fma(a_, vc[u], racc);
+          cd[u] = fma((r > c) ? a_ : 0.0, vr, cd[u]);
+        }
+      }
+      if (in) my[r] += racc;
+    }
+    const double tot = wave_strip_sum(cd);
+    if ((lane & (kWave / kStrip - 1)) == 0 && c0 + pl < n) my[c0 + pl] += tot;
+  }
+  __syncthreads();
+  // y may alias row 0 of spart: each thread reads and writes only its own r
+  for (int r = tid; r < n; r += kBigBlock) {
+    double acc = spart[r];
+#pragma unroll
+    for (int w = 1; w < kBigNW; ++w) acc += spart[(int64_t)w * max_m + r];
+    y[r] = acc;
+  }
+}
+
 // ------------------------------------------------------- tridiagonalise
 // Blocked Householder reduction (lower form), panel width NB. Within a
 // panel, column k = k0 + i is first brought up to date with the panel's
 // earlier vectors (A[k:, k] -= V W[k,:]^T + W V[k,:]^T), its reflector
 // (v, tau, beta) is formed, and w = tau (A22 v - V (W^T v) - W (V^T v)),
 // w -= (tau/2)(w.v) v, where A22 is the trailing matrix as it stood at the
-// start of the panel. After the panel, A22 -= V W^T + W V^T on MFMA. Both
-// triangles of the trailing matrix are kept, so the symv streams whole
-// columns with one multiply-add per element and no cross-lane reduction.
+// start of the panel. After the panel, A22 -= V W^T + W V^T on MFMA over
+// the tiles that meet the lower triangle; only the lower triangle is read.
 // Outputs: d[0..m), e[0..m-1), tau[0..m-2) and v_k in column k of S.
 template <class T>
 __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
@@ -106,9 +200,13 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
   __shared__ double red[kBigNW];
   __shared__ double vk[kNB], wk[kNB], z1[kNB], z2[kNB];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  double* sv = dyn;                     // v (max_m)
-  double* sy = dyn + a.max_m;           // y = A22 v (max_m)
-  T* gsm = (T*)(dyn + 2 * a.max_m);
+  // LDS: v, then one region shared by the symv's per-wave row partials
+  // (kBigNW rows of max_m; row 0 becomes y = A22 v) and, during the trailing
+  // update only, the GEMM staging tiles
+  double* sv = dyn;
+  double* spart = dyn + a.max_m;
+  double* sy = spart;
+  T* gsm = (T*)spart;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -172,34 +270,9 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         // column k above row k+1 becomes the zero part of v_k
         for (int q = tid; q <= k; q += kBigBlock) S[(int64_t)k * ld + q] = T(0);
         // (3) y = A22 v, A22 = the trailing matrix as it stood at the start
-        // of the panel (both triangles kept): one thread per row, columns
-        // streamed with a uniform base address, four partial sums.
-        {
-          const T* A22 = S + (int64_t)(k + 1) * ld + (k + 1);
-          for (int r0 = 0; r0 < n2; r0 += kBigBlock) {
-            const int r = r0 + tid;
-            if (r < n2) {
-              double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-              int jj = 0;
-              // eight column loads in flight per thread
-              for (; jj + 8 <= n2; jj += 8) {
-                double av[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) av[u] = (double)(A22 + (int64_t)(jj + u) * ld)[r];
-                acc0 = fma(av[0], sv[jj], acc0);
-                acc1 = fma(av[1], sv[jj + 1], acc1);
-                acc2 = fma(av[2], sv[jj + 2], acc2);
-                acc3 = fma(av[3], sv[jj + 3], acc3);
-                acc0 = fma(av[4], sv[jj + 4], acc0);
-                acc1 = fma(av[5], sv[jj + 5], acc1);
-                acc2 = fma(av[6], sv[jj + 6], acc2);
-                acc3 = fma(av[7], sv[jj + 7], acc3);
-              }
-              for (; jj < n2; ++jj) acc0 = fma((double)(A22 + (int64_t)jj * ld)[r], sv[jj], acc0);
-              sy[r] = (acc0 + acc1) + (acc2 + acc3);
-            }
-          }
-        }
+        // of the panel, lower triangle only: every element is read once and
+        // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r].
+        symv_lower(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, sy, spart, a.max_m);
         __syncthreads();
         // (4) y -= V (W^T v) + W (V^T v) over the panel's earlier vectors
         if (i > 0) {
@@ -245,8 +318,8 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         const T* V2 = S + (int64_t)k0 * ld + c0;
         const T* W2 = Wb + c0;
         T* C = S + (int64_t)c0 * ld + c0;
-        wg_gemm<T, kBigNW, false, true, false, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
-        wg_gemm<T, kBigNW, false, true, false, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kBigNW, false, true, true, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kBigNW, false, true, true, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
       }
     }
     if (tid == 0) {
@@ -775,7 +848,8 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
 
 template <class T>
 static void launch_tridiag_t(const LargeArgs& a, hipStream_t s) {
-  const size_t lds = vec_lds(a, 2, 8) + gemm_lds_elems<kBigNW>() * sizeof(T);
+  const size_t part = vec_lds(a, kBigNW, 8), gemm = gemm_lds_elems<kBigNW>() * sizeof(T);
+  const size_t lds = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
   hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kBigBlock), lds, s, a);
 }
 

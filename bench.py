@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0
 
 # library kernel (substring of its symbol) -> phase of submat_time_phases
 KERNEL_PHASE = {"k_small": "small-jacobi", "k_gather_large": "gather", "k_tridiagonalise": "tridiagonalise",
-                "k_form_q1": "form-q1", "k_tridiag_ql": "tridiagonal-ql", "k_apply_rotations": "apply-rotations",
+                "k_form_q1": "form-q1", "k_tridiag_eig": "tridiagonal-eig", "k_eig_orth": "eig-reorthogonalise",
+                "k_back_transform": "back-transform",
                 "k_apply_column": "apply-column", "k_adjoint": "adjoint", "k_plan_pattern": "plan-reset"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_1710_10899_amd", "csrc")
@@ -37,24 +38,27 @@ def log(msg: str) -> None:
 
 
 def flops_model(m):
-    """Algorithmic flops per column: forward (10/3)m^3 + 3m^2 (tridiagonal
-    reduction, forming Q, f and the column), adjoint 3m^3 + 5m^2."""
+    """Algorithmic flops per column: forward (14/3)m^3 + 3m^2 (tridiagonal
+    reduction 4/3, forming Q1 4/3, Q = Q1 Z 2, then f and the column),
+    adjoint 3m^3 + 5m^2 (Q M and the symmetric product with Q^T)."""
     m = m.astype("float64")
-    return float(((10.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
+    return float(((14.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
 
 
-def phase_work(m, phase, rotwork):
+def phase_work(m, phase):
     """Algorithmic work of one launch of a phase over all large-order
-    submatrices: (amount, unit, bound)."""
+    submatrices: (amount, unit, bound). The reduction streams the lower
+    triangle of the trailing matrix once per column from HBM (its slab does
+    not fit on chip): sum_k 8 (m-k)^2 / 2 ~ (4/3) m^3 bytes."""
     m = m[m > 64].astype("float64")
     if phase == "tridiagonalise":
-        return float((4.0 / 3.0) * (m ** 3).sum()), "flop", "alu"
+        return float((4.0 / 3.0) * (m ** 3).sum()), "byte", "hbm"
     if phase == "form-q1":
         return float((4.0 / 3.0) * (m ** 3).sum()), "flop", "mfma"
-    if phase == "apply-rotations":
-        return 6.0 * float(rotwork), "flop", "alu"
+    if phase == "back-transform":
+        return float(2.0 * (m ** 3).sum()), "flop", "mfma"
     if phase == "adjoint":
-        return float(4.0 * (m ** 3).sum()), "flop", "mfma"
+        return float(3.0 * (m ** 3).sum()), "flop", "mfma"
     if phase == "gather":
         return float(12.0 * (m ** 2).sum()), "byte", "hbm"
     if phase == "apply-column":
@@ -311,13 +315,12 @@ def main():
     if not args.no_phases:
         ph = sm.time_phases(rp, ci, va, args.p, prec, grad_x=gx)
         counters = _lib.submat_query_counters(torch.cuda.current_stream().cuda_stream, 4)
-        rotwork = counters[3]
         table = {}
         for k, (ms, nl) in ph.items():
             if not nl:
                 continue
             per = ms / nl
-            amount, unit, bound = phase_work(m, k, rotwork)
+            amount, unit, bound = phase_work(m, k)
             row = {"ms_per_launch": round(per, 3), "launches": nl}
             if amount is not None:
                 rate = amount / (per / 1e3)
@@ -337,7 +340,7 @@ def main():
             out["roofline"] = {"kernel": dom, "bound": "latency", "achieved": None, "peak": None,
                                "unit": None, "frac": None, "traffic": measured_traffic(dom),
                                "launch_ms": d["ms_per_launch"]}
-        out["rotation_row_updates"] = rotwork
+        out["inverse_iteration_vectors"] = counters[3]
         log(f"phases {table}")
 
     if not args.no_plain:

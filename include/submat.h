@@ -86,9 +86,15 @@ extern "C" {
                                     replay it (default 1); 0: direct launches */
 #define SUBMAT_OPT_SMALL_MAX 3   /* largest order on the one-wavefront Jacobi path (64) */
 #define SUBMAT_OPT_WS_BYTES 4    /* workspace budget per plan in bytes (0: automatic) */
-#define SUBMAT_OPT_ROT_BATCH 5   /* QL sweeps applied per pass over Q (8 or 16) */
-#define SUBMAT_OPT_TUNE_FILE 6   /* reserved: autotune table is read from the path in the
-                                    environment variable SUBMAT_TUNE_FILE */
+#define SUBMAT_OPT_CLUSTER_TOL 5 /* relative eigenvalue gap (times ||T||) below which the
+                                    tridiagonal eigensolver computes eigenvectors by inverse
+                                    iteration with reorthogonalisation (1e-5), in [0, 1) */
+#define SUBMAT_OPT_TUNE_FILE 6   /* tuning table of workgroups per compute unit: set 1 to
+                                    (re)read the file named by the environment variable
+                                    SUBMAT_TUNE_FILE (lines "kind m_hi blocks_per_cu", as
+                                    written by the package's autotune module), 0 for the
+                                    built-in table; get returns 1 when a file is in use.
+                                    The table is first read at the first call. */
 
 /*
  * Forward: x_vals[rowptr[j] + i] = (f(S_j))[i][c_j] for every column j and
@@ -138,9 +144,10 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
 /*
  * Synchronises `stream` and copies the first n (n <= 8) device counters of the
  * last completed call on the current device: [0] non-positive submatrices,
- * [1] FP64 redos, [2] unconverged, [3] the sum over large-order submatrices of
- * (recorded QL rotations x order), i.e. the row updates the rotation kernel
- * applies (6 flops each). Returns SUBMAT_EINVAL for n outside 1..8 or out NULL.
+ * [1] FP64 redos, [2] unconverged, [3] eigenvectors of the tridiagonal
+ * eigensolver (large-order path) computed by inverse iteration because their
+ * eigenvalue lies in a cluster. Returns SUBMAT_EINVAL for n outside 1..8 or
+ * out NULL.
  */
 int submat_query_counters(void* stream, int64_t* out, int32_t n);
 
@@ -163,7 +170,7 @@ int32_t submat_version(void);
  * that stream, and writes per-phase totals in milliseconds to phase_ms[] and the
  * number of launches to phase_launches[] (arrays of SUBMAT_NUM_PHASES entries).
  * Phase order: plan-reset, small-jacobi, gather, tridiagonalise, form-q1,
- * tridiagonal-ql, apply-rotations, apply-column, adjoint, fallback.
+ * tridiagonal-eig, back-transform, apply-column, adjoint, fallback.
  */
 #define SUBMAT_NUM_PHASES 10
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals,

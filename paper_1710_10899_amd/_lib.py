@@ -33,12 +33,12 @@ SUBMAT_OPT_KAPPA_MAX = 1
 SUBMAT_OPT_USE_GRAPH = 2
 SUBMAT_OPT_SMALL_MAX = 3
 SUBMAT_OPT_WS_BYTES = 4
-SUBMAT_OPT_ROT_BATCH = 5
+SUBMAT_OPT_CLUSTER_TOL = 5
 SUBMAT_OPT_TUNE_FILE = 6
 SUBMAT_NUM_PHASES = 10
 
-PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "form-q1", "tridiagonal-ql",
-          "apply-rotations", "apply-column", "adjoint", "fallback"]
+PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "form-q1", "tridiagonal-eig",
+          "back-transform", "apply-column", "adjoint", "fallback"]
 
 # exported symbol -> (restype, argtypes)
 _P = ctypes.c_void_p

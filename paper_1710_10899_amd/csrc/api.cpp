@@ -27,7 +27,8 @@ struct Options {
   int use_graph = 1;
   int small_max = 64;
   double ws_bytes = 0.0;
-  int rot_batch = 16;
+  double cluster_tol = 1e-5;
+  uint64_t tune_gen = 0;   // bumped whenever the tuning table is reloaded
 };
 Options g_opt;
 std::mutex g_mu;
@@ -87,8 +88,7 @@ struct Chunk {
   int start = 0, count = 0, max_m = 0;
   int64_t slab_bytes = 0;   // S (and Q, W) bytes for this chunk
   int64_t vec_bytes = 0;    // per vector array
-  int64_t rot_bytes = 0;
-  int64_t sw_ints = 0;
+  int64_t escr_bytes = 0;   // eigensolver scratch
 };
 
 struct GraphEntry {
@@ -113,13 +113,13 @@ struct Plan {
   int small_mmax = 0, large_mmax = 0;
   // large-item layout
   DevBuf<int32_t> d_ldm;
-  DevBuf<int64_t> d_off, d_voff, d_roff, d_swoff, d_sqoff, d_sdoff;
+  DevBuf<int64_t> d_off, d_voff, d_eoff, d_sqoff, d_sdoff;
   std::vector<int64_t> h_sqoff, h_sdoff;
   std::vector<Chunk> chunks;
   int64_t saved_q_bytes = 0, saved_bytes = 0;
   // workspace
-  DevBuf<char> S, Q, W, dv, ev, tv, rot;
-  DevBuf<int32_t> sweeps, nsweeps, flags;
+  DevBuf<char> S, Q, W, dv, ev, tv, escr;
+  DevBuf<int32_t> flags;
   DevBuf<int32_t> counters;
   int ncounters = 0;
   // graphs
@@ -184,17 +184,18 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   // large-item layout: chunks bounded by the workspace budget
   const int nl = (int)P.large_items.size();
   std::vector<int32_t> ldm(nl);
-  std::vector<int64_t> off(nl), voff(nl), roff(nl), swoff(nl);
+  std::vector<int64_t> off(nl), voff(nl), eoff(nl);
   P.h_sqoff.resize(nl);
   P.h_sdoff.resize(nl);
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   double budget = g_opt.ws_bytes > 0 ? g_opt.ws_bytes : 0.5 * (double)free_b;
-  // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), rotations 16 (2 m^2 + 64)
+  // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), eigensolver scratch 16 ld^2
   int64_t sq = 0, sd = 0;
   Chunk cur;
   auto item_bytes = [&](int m, int ld) {
-    return 3 * 8 * (int64_t)ld * ld + 4 * 8 * (int64_t)ld + 16 * (2 * (int64_t)m * m + 64) + 4 * (3 * (6 * (int64_t)m + 16));
+    (void)m;
+    return 5 * 8 * (int64_t)ld * ld + 4 * 8 * (int64_t)ld;
   };
   double used = 0;
   for (int g = 0; g < nl; ++g) {
@@ -210,12 +211,10 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
     if (cur.count == 0) cur.start = g;
     off[g] = cur.slab_bytes;
     voff[g] = cur.vec_bytes;
-    roff[g] = cur.rot_bytes;
-    swoff[g] = cur.sw_ints;
+    eoff[g] = cur.escr_bytes;
     cur.slab_bytes += 8 * (int64_t)ld * ld;
     cur.vec_bytes += 8 * (int64_t)ld;
-    cur.rot_bytes += 16 * (2 * (int64_t)m * m + 64);
-    cur.sw_ints += 3 * (6 * (int64_t)m + 16);
+    cur.escr_bytes += 16 * (int64_t)ld * ld;
     cur.max_m = std::max(cur.max_m, m);
     cur.count++;
     used += ib;
@@ -230,23 +229,21 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   P.saved_q_bytes = sq;
   P.saved_bytes = nl ? (sq + sd + 4 * (int64_t)nl) : 0;
 
-  int64_t ws_slab = 0, ws_vec = 0, ws_rot = 0, ws_sw = 0;
+  int64_t ws_slab = 0, ws_vec = 0, ws_escr = 0;
   int max_count = 0;
   for (auto& c : P.chunks) {
     ws_slab = std::max(ws_slab, c.slab_bytes);
     ws_vec = std::max(ws_vec, c.vec_bytes);
-    ws_rot = std::max(ws_rot, c.rot_bytes);
-    ws_sw = std::max(ws_sw, c.sw_ints);
+    ws_escr = std::max(ws_escr, c.escr_bytes);
     max_count = std::max(max_count, c.count);
   }
   if ((rc = P.d_small.alloc(P.small_items.size())) || (rc = P.d_large.alloc(nl)) || (rc = P.d_ldm.alloc(nl)) ||
-      (rc = P.d_off.alloc(nl)) || (rc = P.d_voff.alloc(nl)) || (rc = P.d_roff.alloc(nl)) ||
-      (rc = P.d_swoff.alloc(nl)) || (rc = P.d_sqoff.alloc(nl)) || (rc = P.d_sdoff.alloc(nl)))
+      (rc = P.d_off.alloc(nl)) || (rc = P.d_voff.alloc(nl)) || (rc = P.d_eoff.alloc(nl)) ||
+      (rc = P.d_sqoff.alloc(nl)) || (rc = P.d_sdoff.alloc(nl)))
     return rc;
   if ((rc = P.S.alloc(ws_slab)) || (rc = P.Q.alloc(ws_slab)) || (rc = P.W.alloc(ws_slab)) ||
       (rc = P.dv.alloc(ws_vec)) || (rc = P.ev.alloc(ws_vec)) || (rc = P.tv.alloc(ws_vec)) ||
-      (rc = P.rot.alloc(ws_rot)) || (rc = P.sweeps.alloc(ws_sw)) || (rc = P.nsweeps.alloc(max_count)) ||
-      (rc = P.flags.alloc(std::max(max_count, 1))))
+      (rc = P.escr.alloc(ws_escr)) || (rc = P.flags.alloc(std::max(max_count, 1))))
     return rc;
   // one work counter per persistent launch of the longest sequence (the
   // per-column path launches up to 7 kernels per column)
@@ -261,8 +258,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   HIP_TRY(up(P.d_ldm.p, ldm.data(), nl * 4));
   HIP_TRY(up(P.d_off.p, off.data(), nl * 8));
   HIP_TRY(up(P.d_voff.p, voff.data(), nl * 8));
-  HIP_TRY(up(P.d_roff.p, roff.data(), nl * 8));
-  HIP_TRY(up(P.d_swoff.p, swoff.data(), nl * 8));
+  HIP_TRY(up(P.d_eoff.p, eoff.data(), nl * 8));
   HIP_TRY(up(P.d_sqoff.p, P.h_sqoff.data(), nl * 8));
   HIP_TRY(up(P.d_sdoff.p, P.h_sdoff.data(), nl * 8));
   HIP_TRY(hipStreamSynchronize(stream));
@@ -273,7 +269,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
 }
 
 // ----------------------------------------------------------- launch sequence
-enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_FORMQ1, PH_QL, PH_ROT, PH_COLUMN, PH_ADJOINT, PH_FALLBACK, PH_N };
+enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_FORMQ1, PH_EIG, PH_BACK, PH_COLUMN, PH_ADJOINT, PH_FALLBACK, PH_N };
 
 struct Call {
   const void* vals;
@@ -339,8 +335,7 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
   a.ldm = P.d_ldm.p + g_first;
   a.off = P.d_off.p + g_first;
   a.voff = P.d_voff.p + g_first;
-  a.roff = P.d_roff.p + g_first;
-  a.swoff = P.d_swoff.p + g_first;
+  a.eoff = P.d_eoff.p + g_first;
   if (c.saved) {
     a.qoff = P.d_sqoff.p + g_first;
     a.doff = P.d_sdoff.p + g_first;
@@ -358,14 +353,12 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
   a.W = P.W.p;
   a.e = P.ev.p;
   a.tau = P.tv.p;
-  a.rot = P.rot.p;
-  a.sweeps = P.sweeps.p;
-  a.nsweeps = P.nsweeps.p + (g_first - P.chunks[chunk].start);
+  a.escr = P.escr.p;
   a.flags = (c.saved ? (int32_t*)(c.saved + P.saved_bytes - 4 * (int64_t)P.large_items.size()) + g_first
                      : P.flags.p + (g_first - P.chunks[chunk].start));
   a.p = c.p;
   a.kappa_max = g_opt.kappa_max;
-  a.rot_batch = g_opt.rot_batch;
+  a.cluster_tol = g_opt.cluster_tol;
   a.x = c.x;
   a.gx = c.gx;
   a.ga = c.ga;
@@ -381,7 +374,6 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
   LargeArgs a = make_large(P, c, chunk, g_first, count, max_m);
   a.status = ctx->status.p;
   a.lds_limit = ctx->lds_limit;
-  a.ql_bpc = tuned_ql_blocks_per_cu(max_m);
   a.fp64 = fp64;
   a.only_flagged = only_flagged;
   const int tune_cu = per_column ? 0 : tuned_blocks_per_cu(max_m, fp64);
@@ -393,8 +385,18 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
     next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(a, s));
     next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(a, s));
     next(); HIP_SEQ(ph < 0 ? PH_FORMQ1 : ph, launch_form_q1(a, s));
-    HIP_SEQ(ph < 0 ? PH_QL : ph, launch_tridiag_ql(a, s));
-    next(); HIP_SEQ(ph < 0 ? PH_ROT : ph, launch_apply_rotations(a, s));
+    {
+      // the eigensolver's workgroups share a compute unit's LDS
+      LargeArgs b = a;
+      const int fit = (int)(ctx->lds_limit / (int64_t)(eig_lds_bytes(max_m) + 2048));
+      const int bpc = std::max(1, std::min(tuned_eig_blocks_per_cu(max_m), fit));
+      b.grid = per_column ? 1 : persistent_grid(ctx, count, bpc);
+      next();
+      b.work_ctr = a.work_ctr;
+      HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_tridiag_eig(b, s));
+    }
+    next(); HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_eig_orth(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(a, s));
   }
   next();
   if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(a, s));
@@ -460,7 +462,8 @@ int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& t
 int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
   std::vector<uintptr_t> key = {(uintptr_t)c.vals, (uintptr_t)c.vdtype, (uintptr_t)c.p, (uintptr_t)c.precision,
                                 (uintptr_t)c.x, (uintptr_t)c.gx, (uintptr_t)c.ga, (uintptr_t)c.saved,
-                                (uintptr_t)c.bwd, (uintptr_t)(g_opt.kappa_max * 1e3), (uintptr_t)g_opt.rot_batch};
+                                (uintptr_t)c.bwd, (uintptr_t)(g_opt.kappa_max * 1e3), (uintptr_t)(g_opt.cluster_tol * 1e12),
+                                (uintptr_t)g_opt.tune_gen};
   GraphEntry* hit = nullptr;
   for (auto& g : P.graphs)
     if (g.key == key) hit = &g;
@@ -616,9 +619,14 @@ int submat_set_option(int32_t key, double value) {
       g_opt.ws_bytes = value;
       g_plans.clear();
       return SUBMAT_OK;
-    case SUBMAT_OPT_ROT_BATCH:
-      if (value != 8 && value != 16) return SUBMAT_EINVAL;
-      g_opt.rot_batch = (int)value;
+    case SUBMAT_OPT_CLUSTER_TOL:
+      if (!(value >= 0.0 && value < 1.0)) return SUBMAT_EINVAL;
+      g_opt.cluster_tol = value;
+      return SUBMAT_OK;
+    case SUBMAT_OPT_TUNE_FILE:
+      if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
+      reload_tuning(value == 1.0);
+      g_opt.tune_gen++;
       return SUBMAT_OK;
     default:
       return SUBMAT_EINVAL;
@@ -632,7 +640,8 @@ double submat_get_option(int32_t key) {
     case SUBMAT_OPT_USE_GRAPH: return g_opt.use_graph;
     case SUBMAT_OPT_SMALL_MAX: return g_opt.small_max;
     case SUBMAT_OPT_WS_BYTES: return g_opt.ws_bytes;
-    case SUBMAT_OPT_ROT_BATCH: return g_opt.rot_batch;
+    case SUBMAT_OPT_CLUSTER_TOL: return g_opt.cluster_tol;
+    case SUBMAT_OPT_TUNE_FILE: return tuning_from_file() ? 1.0 : 0.0;
     default: return NAN;
   }
 }
@@ -657,7 +666,7 @@ void submat_release(void) {
   g_plans.clear();
 }
 
-int32_t submat_version(void) { return 100; }
+int32_t submat_version(void) { return 110; }
 
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                        int32_t p, int32_t dtype, int32_t precision, void* x_vals, const void* grad_x, void* grad_a,

@@ -2,7 +2,8 @@
 //
 // The table maps an upper bound on the submatrix order to the number of
 // workgroups per compute unit: kind 0 = FP32 persistent kernels, kind 1 =
-// FP64 persistent kernels, kind 2 = QL kernel. Defaults come from LDS and
+// FP64 persistent kernels, kind 2 = tridiagonal eigensolver (capped by its
+// LDS use at launch). Defaults come from LDS and
 // register use of the kernels; a file written by the package's autotune
 // script (environment variable SUBMAT_TUNE_FILE, lines
 // "kind m_hi blocks_per_cu") overrides them.
@@ -22,13 +23,15 @@ struct Entry {
 
 std::vector<Entry> g_table;
 bool g_loaded = false;
+bool g_from_file = false;
 std::mutex g_tmu;
 
-void load_locked() {
+void load_locked(bool use_file) {
   g_table = {{1, 128, 8}, {1, 256, 4}, {1, 1024, 2}, {1, 1 << 30, 1},
              {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1},
-             {2, 1 << 30, 2}};
-  const char* path = std::getenv("SUBMAT_TUNE_FILE");
+             {2, 256, 8}, {2, 512, 6}, {2, 1024, 4}, {2, 1 << 30, 1}};
+  g_from_file = false;
+  const char* path = use_file ? std::getenv("SUBMAT_TUNE_FILE") : nullptr;
   if (path && *path) {
     if (FILE* f = std::fopen(path, "r")) {
       std::vector<Entry> t;
@@ -36,7 +39,10 @@ void load_locked() {
       while (std::fscanf(f, "%d %d %d", &e.fp64, &e.m_hi, &e.bpc) == 3)
         if (e.bpc >= 1 && e.bpc <= 32 && e.m_hi >= 1 && e.fp64 >= 0 && e.fp64 <= 2) t.push_back(e);
       std::fclose(f);
-      if (!t.empty()) g_table = t;
+      if (!t.empty()) {
+        g_table = t;
+        g_from_file = true;
+      }
     }
   }
   g_loaded = true;
@@ -44,14 +50,20 @@ void load_locked() {
 
 }  // namespace
 
-void reload_tuning() {
+void reload_tuning(bool use_file) {
   std::lock_guard<std::mutex> lk(g_tmu);
-  load_locked();
+  load_locked(use_file);
+}
+
+bool tuning_from_file() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_loaded) load_locked(true);
+  return g_from_file;
 }
 
 static int lookup(int kind, int max_m) {
   std::lock_guard<std::mutex> lk(g_tmu);
-  if (!g_loaded) load_locked();
+  if (!g_loaded) load_locked(true);
   int best = 1, best_hi = 1 << 30;
   bool found = false;
   for (const Entry& e : g_table) {
@@ -67,6 +79,6 @@ static int lookup(int kind, int max_m) {
 
 int tuned_blocks_per_cu(int max_m, int fp64) { return lookup(fp64 ? 1 : 0, max_m); }
 
-int tuned_ql_blocks_per_cu(int max_m) { return lookup(2, max_m); }
+int tuned_eig_blocks_per_cu(int max_m) { return lookup(2, max_m); }
 
 }  // namespace submat

@@ -11,7 +11,7 @@ enum StatusSlot : int {
   ST_NONPOS = 0,      // submatrices with an eigenvalue <= 0
   ST_FALLBACK = 1,    // submatrices redone in FP64 by the mixed path
   ST_UNCONV = 2,      // eigensolver did not converge
-  ST_ROTWORK = 3,     // sum of (recorded QL rotations x order): row updates of the rotation kernel
+  ST_INVITER = 3,     // eigenvectors computed by inverse iteration (eigenvalue clusters)
   ST_NSLOTS = 64,
 };
 
@@ -67,27 +67,22 @@ struct LargeArgs {
   const int64_t* off;     // per item: S and W slab offset
   const int64_t* qoff;    // per item: Q slab offset (workspace or saved buffer)
   const int64_t* voff;    // per item: offset of its e / tau vectors
-  const int64_t* doff;    // per item: offset of d (eigenvalues after QL)
-  const int64_t* roff;    // per item: offset of its rotation pairs
-  const int64_t* swoff;   // per item: offset (in int32 units) in the sweep table
+  const int64_t* doff;    // per item: offset of d (eigenvalues after the eigensolver)
+  const int64_t* eoff;    // per item: offset of its eigensolver scratch (2 ld^2 doubles)
   int n_items;
   int max_m;
-  void* S;                // slab base (Householder vectors, later scratch)
+  void* S;                // slab base (Householder vectors, then Z^T)
   void* Q;                // slab base (eigenvectors)
-  void* W;                // slab base (adjoint scratch)
-  void* d;                // per item vectors (eigenvalues after QL)
+  void* W;                // slab base (Q1, adjoint scratch)
+  void* d;                // per item vectors (eigenvalues after the eigensolver)
   void* e;
   void* tau;
-  void* rot;              // rotation pairs (c, s)
-  int32_t* sweeps;        // per sweep: hi, lo, rotation offset (3 ints)
-  int32_t* nsweeps;       // per item
+  void* escr;             // eigensolver scratch
   int32_t* flags;         // per item: bit0 nonpositive, bit1 fallback, bit2 unconverged
   int p;
   double kappa_max;
-  int rot_batch;
-  int ql_items;           // submatrices per wave in the QL kernel (set at launch)
+  double cluster_tol;     // relative eigenvalue gap below which inverse iteration is used
   int lds_limit;          // device limit on LDS bytes per workgroup
-  int ql_bpc;             // QL blocks per compute unit (tuning table)
   void* x;                // forward output (value type vdtype)
   const void* gx;         // backward input
   void* ga;               // backward output (accumulated)
@@ -102,9 +97,10 @@ enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
 hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s);
-hipError_t launch_tridiag_ql(const LargeArgs& a, hipStream_t s);
-hipError_t launch_apply_rotations(const LargeArgs& a, hipStream_t s);
-hipError_t launch_check_spectrum(const LargeArgs& a, hipStream_t s);
+hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);
+hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s);
+hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s);
+size_t eig_lds_bytes(int max_m);
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s);
 

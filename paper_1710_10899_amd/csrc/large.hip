@@ -1,19 +1,15 @@
-// Large-order path (m > 64): one workgroup per submatrix for the dense
-// stages, one lane per submatrix for the tridiagonal QL iteration.
+// Large-order path (m > 64): one workgroup per submatrix.
 //
 //   gather      S_j from CSR into an HBM slab (Section 3.1), symmetrised
 //   tridiag     blocked Householder reduction S = Q1 T Q1^T (lower form): per
-//               panel of NB columns a row-parallel symv per column, and one
+//               panel of NB columns a lower-triangle symv per column, and one
 //               rank-2*NB trailing update on MFMA
 //   form_q1     Q1 accumulated explicitly from compact-WY blocks of NB
-//               reflectors, products on MFMA
-//   ql          implicit QL with Wilkinson shifts on T (d, e in LDS); the
-//               eigenvalues replace d and every plane rotation is recorded,
-//               sweep by sweep
-//   rotations   Q = Q1 * (all rotations): each thread owns a row of Q and
-//               applies a batch of K sweeps in one pass over it (sweep s lags
-//               sweep s-1 by two columns, so a window of 2K values suffices);
-//               rotation coefficients are staged in LDS tables
+//               reflectors, products on MFMA (into the W slab)
+//   eig         T = Z diag(lambda) Z^T in FP64: bisection for the
+//               eigenvalues, twisted factorisation / inverse iteration for
+//               the eigenvectors (Z^T into the S slab)
+//   back        Q = Q1 Z, one m x m x m product on MFMA
 //   column      x = Q (f(lambda) o Q[c,:]^T) into X's value segment
 //               (Sections 3.3-3.4)
 //   adjoint     D = Q sym(G o (a b^T)) Q^T on MFMA, scattered into dA's
@@ -361,8 +357,8 @@ __global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
     const T* S = at<T>((const void*)a.S, a.off[it]);
-    T* Q = at<T>(a.Q, a.qoff[it]);
-    T* Wm = at<T>(a.W, a.off[it]);
+    T* Q = at<T>(a.W, a.off[it]);        // Q1 is formed in the W slab
+    T* Wm = at<T>(a.escr, a.eoff[it]);   // NB x (m-1) scratch
     const T* tau = at<T>((const void*)a.tau, a.voff[it]);
     const int64_t tot = (int64_t)ld * ld;
     for (int64_t q = tid; q < tot; q += kBigBlock) {
@@ -433,295 +429,523 @@ __global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
   }
 }
 
-// ---------------------------------------------------------- QL on T
-__device__ __forceinline__ void store_pair(double* p, double c, double s) {
-  *(double2*)p = make_double2(c, s);
-}
-__device__ __forceinline__ void store_pair(float* p, float c, float s) {
-  *(float2*)p = make_float2(c, s);
+// --------------------------------------------- tridiagonal eigensolver
+// Eigen-decomposition of T = tridiag(e, d, e) in FP64 (Section 3.2 leaves
+// the dense eigensolver open; this is bisection plus inverse iteration):
+//  * off-diagonals below eps * sqrt(|d_i d_i+1|) are set to zero, which
+//    splits T into unreduced blocks; eigenvalue index j belongs to the block
+//    holding row j;
+//  * eigenvalue j: bisection on the Sturm count of its block (one lane per
+//    eigenvalue), from Gershgorin bounds down to a few ulps;
+//  * eigenvector of an eigenvalue whose neighbours in its block are further
+//    than ctol * ||T|| away: twisted factorisation T - lambda I =
+//    N_r D_r N_r^T with the twist r minimising |gamma_r|, then
+//    z_r = 1, z_i = -L_i z_i+1 (i < r), z_i+1 = -U_i z_i (i >= r);
+//  * a cluster of closer eigenvalues is handled by one lane, member after
+//    member: inverse iteration with LDL^T solves from a seeded start vector,
+//    each iterate orthogonalised (modified Gram-Schmidt) against the
+//    cluster's earlier vectors, with perturbed shifts for coincident values.
+// Eigenvalues replace d (ascending within each block); eigenvector j is
+// stored as row j of Y (Y[j][i] at i*ld + j, so a lane's stores of one
+// component coalesce across lanes) in the S slab. Two FP64 m x m scratch
+// arrays (lane j owns column j) hold the factors.
+constexpr int kEigBlock = 256;
+constexpr int kEigNW = kEigBlock / kWave;
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
+constexpr double kSafeMin = 2.2250738585072014e-308;
+constexpr int kInvIterMax = 5;
+constexpr int kOrthB = 16;  // eigenvectors per block of the local reorthogonalisation
+static_assert(kOrthB * kOrthB == kEigBlock, "one thread per entry of a block Gram matrix");
+
+// Counter-based uniform deviate in (-1, 1): the splitmix64 finaliser
+// (Steele, Lea, Flood 2014) of a 64-bit key.
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
-// One lane per submatrix, P submatrices per wave, d and e in LDS (FP64).
-// Implicit QL with a Wilkinson shift on the unreduced block [l, mm]; each
-// sweep runs i = mm-1 down to l and records its rotations (c, s): columns
-// (i, i+1) of Q become (c q_i - s q_{i+1}, s q_i + c q_{i+1}).
-// Sweep table entry: hi, lo, offset of its first rotation.
-template <class T>
-__global__ __launch_bounds__(64) void k_tridiag_ql(LargeArgs a) {
-  extern __shared__ double dyn[];
-  const int P = a.ql_items;
-  const int LDL = a.max_m + 1;
-  const int lane = threadIdx.x;
-  const int it = blockIdx.x * P + lane;
-  if (lane >= P || it >= a.n_items) return;
-  if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) return;
-  const int j = a.items[it];
-  const int m = a.rowptr[j + 1] - a.rowptr[j];
-  double* d = dyn + (int64_t)lane * LDL;
-  double* e = dyn + (int64_t)(P + lane) * LDL;
-  T* dg = at<T>(a.d, a.doff[it]);
-  const T* eg = at<T>((const void*)a.e, a.voff[it]);
-  for (int k = 0; k < m; ++k) {
-    d[k] = (double)dg[k];
-    e[k] = (double)eg[k];
+// 1/q from the hardware reciprocal and two Newton steps (relative error a
+// few ulps; |q| >= pivmin >= the smallest normal, so 1/q is finite).
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
+// Number of eigenvalues of block [s, t) below x (Sturm sequence of the
+// LDL^T factorisation of T - xI; tiny pivots replaced by -pivmin, so that
+// |e^2 / q| <= e^2 / pivmin stays finite).
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int s, int t, double x,
+                                           double pivmin) {
+  double q = d[s] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = s + 1; i < t; ++i) {
+    q = fma(-e2[i - 1], recip(q), d[i] - x);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
   }
-  T* rot = at<T>(a.rot, a.roff[it]);
-  int32_t* sw = a.sweeps + a.swoff[it];
-  const int64_t rot_cap = 2 * (int64_t)m * m + 64;
-  const int sw_cap = 6 * m + 16;
-  const double eps = Eps<T>::v;
-  int64_t nrot = 0;
-  int nsw = 0;
-  int flags = 0;
-  e[m - 1] = 0.0;
-  for (int l = 0; l < m && !(flags & LF_UNCONV); ++l) {
-    int iter = 0;
-    for (;;) {
-      // first negligible off-diagonal at or after l, eight entries per step
-      int mm = m - 1;
-      for (int k8 = l; k8 < m - 1; k8 += 8) {
-        int hit = -1;
-#pragma unroll
-        for (int u = 7; u >= 0; --u) {
-          const int kk = k8 + u;
-          if (kk < m - 1 && fabs(e[kk]) <= eps * (fabs(d[kk]) + fabs(d[kk + 1]))) hit = kk;
-        }
-        if (hit >= 0) {
-          mm = hit;
-          break;
-        }
-      }
-      if (mm == l) break;
-      if (++iter > 40 || nsw >= sw_cap || nrot + (mm - l) > rot_cap) {
-        flags |= LF_UNCONV;
-        break;
-      }
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = hypot(g, 1.0);
-      g = d[mm] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-      double s = 1.0, c = 1.0, pp = 0.0;
-      const int64_t base = nrot;
-      bool early = false;
-      // d[i+1] of iteration i is the d[i] that iteration i+1 read (the sweep
-      // only writes d[i+2] before it), so it is carried in a register
-      double dnext = d[mm];
-      double di = d[mm - 1], ei = e[mm - 1];
-      // d[i-1], e[i-1] were read one iteration earlier; d[i-2], e[i-2] are
-      // requested now, so no LDS read is waited on in the rotation chain
-      double dn = mm - 2 >= l ? d[mm - 2] : 0.0, en = mm - 2 >= l ? e[mm - 2] : 0.0;
-      for (int i = mm - 1; i >= l; --i) {
-        double dnn = 0.0, enn = 0.0;
-        if (i - 2 >= l) { dnn = d[i - 2]; enn = e[i - 2]; }
-        const double f = s * ei;
-        const double b = c * ei;
-        // r = hypot(f, g) and 1/r from one reciprocal square root refined by
-        // two Newton steps; the scaled fallback guards against overflow
-        const double af = fabs(f), ag = fabs(g);
-        const double big = af > ag ? af : ag;
-        double rinv;
-        if (big > 1e150 || big < 1e-150) {
-          r = hypot(f, g);
-          rinv = r != 0.0 ? 1.0 / r : 0.0;
-        } else {
-          const double x2 = fma(f, f, g * g);
-          double y = __builtin_amdgcn_rsq(x2);
-          double hx = x2 * y;
-          y = fma(0.5 * y, fma(-hx, y, 1.0), y);
-          hx = x2 * y;
-          y = fma(0.5 * y, fma(-hx, y, 1.0), y);
-          rinv = y;
-          r = x2 * y;
-        }
-        e[i + 1] = r;
-        if (r == 0.0) {
-          d[i + 1] = dnext - pp;
-          e[mm] = 0.0;
-          early = true;
-          break;
-        }
-        s = f * rinv;
-        c = g * rinv;
-        g = dnext - pp;
-        r = (di - g) * s + 2.0 * c * b;
-        pp = s * r;
-        d[i + 1] = g + pp;
-        g = c * r - b;
-        store_pair(rot + 2 * nrot, (T)c, (T)s);
-        ++nrot;
-        dnext = di;
-        di = dn;
-        ei = en;
-        dn = dnn;
-        en = enn;
-      }
-      const int cnt = (int)(nrot - base);
-      if (cnt > 0) {
-        sw[3 * nsw + 0] = mm - 1;
-        sw[3 * nsw + 1] = mm - cnt;
-        sw[3 * nsw + 2] = (int32_t)base;
-        ++nsw;
-      }
-      if (early) continue;
-      d[l] -= pp;
-      e[l] = g;
-      e[mm] = 0.0;
+  return cnt;
+}
+
+__device__ __forceinline__ double guard_pivot(double D, double tol) {
+  return fabs(D) < tol ? (D < 0.0 ? -tol : tol) : D;
+}
+
+// Twisted-factorisation eigenvector of block [s, t) for shift lam, left
+// unnormalised in column jj of Z (z_r = 1). Returns false when the result
+// is not finite or its residual |gamma_r| / ||z|| is not small.
+__device__ bool twisted_vector(const double* d, const double* e, int s, int t, double lam, double tol,
+                               double rtol, double* Z, double* U, int ld, int jj, double& nrm2) {
+  double Dp = guard_pivot(d[s] - lam, tol);
+  for (int i = s; i < t - 1; ++i) {
+    const double L = e[i] / Dp;
+    Z[(int64_t)i * ld + jj] = L;
+    Dp = guard_pivot((d[i + 1] - lam) - L * e[i], tol);
+  }
+  double Dm = guard_pivot(d[t - 1] - lam, tol);
+  double gbest = fabs(Dm - (t - 1 > s ? Z[(int64_t)(t - 2) * ld + jj] * e[t - 2] : 0.0));
+  int r = t - 1;
+  for (int i = t - 2; i >= s; --i) {
+    const double Ui = e[i] / Dm;
+    U[(int64_t)i * ld + jj] = Ui;
+    Dm = guard_pivot((d[i] - lam) - Ui * e[i], tol);
+    const double g = fabs(Dm - (i > s ? Z[(int64_t)(i - 1) * ld + jj] * e[i - 1] : 0.0));
+    if (g < gbest) {
+      gbest = g;
+      r = i;
     }
   }
-  a.nsweeps[it] = nsw;
-  // spectrum checks: lambda_min <= 0 has no real inverse p-th root; in the
-  // FP32 pass an estimated condition number above kappa_max sends the
-  // submatrix to the FP64 pass
-  double lmin = INFINITY, lmax = -INFINITY;
-  for (int k = 0; k < m; ++k) {
-    const double v = d[k];
-    lmin = fmin(lmin, v);
-    lmax = fmax(lmax, v);
-    dg[k] = (T)v;
+  double n2 = 1.0, zn = 1.0;
+  for (int i = t - 2; i >= s; --i) {
+    if (i < r) {
+      const double z = -Z[(int64_t)i * ld + jj] * zn;
+      Z[(int64_t)i * ld + jj] = z;
+      n2 = fma(z, z, n2);
+      zn = z;
+    }
   }
-  if (!a.fp64) {
-    if ((flags & LF_UNCONV) || !(lmin > 0.0) || lmax > a.kappa_max * lmin) flags = LF_FALLBACK;
-  } else if (!(lmin > 0.0)) {
-    flags |= LF_NONPOS;
+  Z[(int64_t)r * ld + jj] = 1.0;
+  double zp = 1.0;
+  for (int i = s; i < t - 1; ++i) {
+    if (i >= r) {
+      const double z = -U[(int64_t)i * ld + jj] * zp;
+      Z[(int64_t)(i + 1) * ld + jj] = z;
+      n2 = fma(z, z, n2);
+      zp = z;
+    }
   }
-  if (a.only_flagged) a.flags[it] = flags | LF_FALLBACK;
-  else a.flags[it] = flags;
-  if (flags & LF_NONPOS) atomicAdd((unsigned long long*)&a.status[ST_NONPOS], 1ull);
-  if (a.fp64 && (flags & LF_UNCONV)) atomicAdd((unsigned long long*)&a.status[ST_UNCONV], 1ull);
-  if (!a.fp64 && (flags & LF_FALLBACK)) atomicAdd((unsigned long long*)&a.status[ST_FALLBACK], 1ull);
-  atomicAdd((unsigned long long*)&a.status[ST_ROTWORK], (unsigned long long)(nrot * m));
+  nrm2 = n2;
+  return isfinite(n2) && gbest <= rtol * sqrt(n2);
 }
 
-// ------------------------------------------------------ apply rotations
-// Q <- Q * G_1 * G_2 * ... (all recorded rotations, in order). A batch of K
-// sweeps is applied in one pass over each row: at step t sweep s acts on
-// columns (P, P+1), P = H - t + 2s. The logical window slot i (column
-// H - t + i) lives in register (i - t) mod 2K, so nothing is shifted; the
-// step loop is unrolled over 2K steps per LDS table chunk. Inactive
-// (sweep, step) pairs are identity rotations in the table. Each thread
-// carries RPT rows, so every coefficient read from LDS serves RPT rows.
-template <class T, int K, int RPT>
-__global__ __launch_bounds__(kBlock) void k_apply_rotations(LargeArgs a) {
-  constexpr int TS = 2 * K;
+// Inverse iteration for the k eigenvalues lam[j0 .. j0+k) of block [s, t),
+// one lane, member by member; results (unit norm) in columns j0.. of Z.
+// Column j of U holds the iterate, column j of Z the LDL^T multipliers
+// until the member is done. Returns the number of members that did not
+// converge.
+__device__ int cluster_vectors(const double* d, const double* e, const double* lam, int s, int t, int j0, int k,
+                               double tol, double rtol, double* Z, double* U, int ld, uint64_t seed) {
+  int bad = 0;
+  double lprev = 0.0;
+  for (int c = 0; c < k; ++c) {
+    const int jc = j0 + c;
+    double lc = lam[jc];
+    if (c > 0) {
+      const double pert = 10.0 * kUnitRoundoff * fmax(fabs(lc), tol);
+      if (lc - lprev < pert) lc = lprev + pert;
+    }
+    lprev = lc;
+    double* y = U + jc;
+    double* L = Z + jc;
+    double nb = 0.0;
+    for (int i = s; i < t; ++i) {
+      const double b = hash_unit(seed ^ ((uint64_t)jc << 32) ^ (uint64_t)i);
+      y[(int64_t)i * ld] = b;
+      nb = fma(b, b, nb);
+    }
+    double sc = 1.0 / sqrt(nb);
+    for (int i = s; i < t; ++i) y[(int64_t)i * ld] *= sc;
+    int conv = 0;
+    for (int iter = 0; iter < kInvIterMax && conv < 2; ++iter) {
+      // (T - lc I) y <- y: LDL^T without pivoting (guarded pivots)
+      double D = guard_pivot(d[s] - lc, tol);
+      double w = y[(int64_t)s * ld];
+      for (int i = s; i < t - 1; ++i) {
+        const double Li = e[i] / D;
+        L[(int64_t)i * ld] = Li;
+        y[(int64_t)i * ld] = w / D;
+        w = y[(int64_t)(i + 1) * ld] - Li * w;
+        D = guard_pivot((d[i + 1] - lc) - Li * e[i], tol);
+      }
+      double yi = w / D;
+      y[(int64_t)(t - 1) * ld] = yi;
+      for (int i = t - 2; i >= s; --i) {
+        yi = y[(int64_t)i * ld] - L[(int64_t)i * ld] * yi;
+        y[(int64_t)i * ld] = yi;
+      }
+      // orthogonalise against the cluster's finished vectors
+      for (int q = 0; q < c; ++q) {
+        const double* zq = Z + (j0 + q);
+        double dot = 0.0;
+        for (int i = s; i < t; ++i) dot = fma(y[(int64_t)i * ld], zq[(int64_t)i * ld], dot);
+        for (int i = s; i < t; ++i) y[(int64_t)i * ld] = fma(-dot, zq[(int64_t)i * ld], y[(int64_t)i * ld]);
+      }
+      double n2 = 0.0;
+      for (int i = s; i < t; ++i) n2 = fma(y[(int64_t)i * ld], y[(int64_t)i * ld], n2);
+      const double nrm = sqrt(n2);
+      // the start had unit norm, so 1/nrm estimates the residual
+      if (isfinite(nrm) && nrm > 0.0 && 1.0 <= rtol * nrm) ++conv;
+      sc = (isfinite(nrm) && nrm > 0.0) ? 1.0 / nrm : 0.0;
+      for (int i = s; i < t; ++i) y[(int64_t)i * ld] *= sc;
+    }
+    if (conv == 0) ++bad;
+    for (int i = s; i < t; ++i) L[(int64_t)i * ld] = y[(int64_t)i * ld];
+  }
+  return bad;
+}
+
+template <class T>
+__global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
+  extern __shared__ double dyn[];
   __shared__ int s_item;
-  __shared__ int s_hi[K], s_lo[K], s_off[K];
-  __shared__ T tab[TS][K][2];
-  const int tid = threadIdx.x;
+  __shared__ double red[4 * kEigNW];
+  __shared__ int ired[2 * kEigNW];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int M = a.max_m;
+  double* d = dyn;
+  double* e = dyn + M;
+  double* e2 = dyn + 2 * M;  // e^2 during bisection, then 1/||z|| per eigenvector
+  double* lam = dyn + 3 * M;
+  int* bs = (int*)(dyn + 4 * M);  // start of the unreduced block holding row i
+  int* be = bs + M;               // its end (exclusive)
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
-    if (skip_item(a, it)) continue;
+    if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) continue;
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
-    T* Q = at<T>(a.Q, a.qoff[it]);
-    const T* rot = at<T>((const void*)a.rot, a.roff[it]);
-    const int32_t* sw = a.sweeps + a.swoff[it];
-    const int nsw = a.nsweeps[it];
-    for (int b0 = 0; b0 < nsw; b0 += K) {
-      const int nb = (nsw - b0) < K ? (nsw - b0) : K;
-      __syncthreads();
-      if (tid < K) {
-        if (tid < nb) {
-          s_hi[tid] = sw[3 * (b0 + tid) + 0];
-          s_lo[tid] = sw[3 * (b0 + tid) + 1];
-          s_off[tid] = sw[3 * (b0 + tid) + 2];
-        } else {
-          s_hi[tid] = -1;  // empty sweep: never active
-          s_lo[tid] = 1;
-          s_off[tid] = 0;
-        }
+    T* dg = at<T>(a.d, a.doff[it]);
+    const T* eg = at<T>((const void*)a.e, a.voff[it]);
+    T* Y = at<T>(a.S, a.off[it]);
+    double* Z = at<double>(a.escr, a.eoff[it]);
+    double* U = Z + (int64_t)ld * ld;
+    for (int i = tid; i < m; i += kEigBlock) {
+      const double di = (double)dg[i];
+      double ei = 0.0;
+      if (i + 1 < m) {
+        ei = (double)eg[i];
+        const double dn = (double)dg[i + 1];
+        if (fabs(ei) <= kUnitRoundoff * sqrt(fabs(di)) * sqrt(fabs(dn))) ei = 0.0;
       }
-      __syncthreads();
-      int H = -1, L = m;
-      for (int s = 0; s < K; ++s) {
-        if (s_hi[s] >= 0) {
-          H = s_hi[s] > H ? s_hi[s] : H;
-          L = s_lo[s] < L ? s_lo[s] : L;
-        }
+      d[i] = di;
+      e[i] = ei;
+      e2[i] = ei * ei;
+    }
+    __syncthreads();
+    double tn = 0.0, glo = INFINITY, ghi = -INFINITY, emax2 = 0.0;
+    for (int i = tid; i < m; i += kEigBlock) {
+      const double el = i > 0 ? fabs(e[i - 1]) : 0.0, er = fabs(e[i]);
+      tn = fmax(tn, fabs(d[i]) + el + er);
+      glo = fmin(glo, d[i] - el - er);
+      ghi = fmax(ghi, d[i] + el + er);
+      emax2 = fmax(emax2, e2[i]);
+    }
+    tn = wave_max(tn);
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    emax2 = wave_max(emax2);
+    if (lane == 0) {
+      red[wv] = tn;
+      red[kEigNW + wv] = glo;
+      red[2 * kEigNW + wv] = ghi;
+      red[3 * kEigNW + wv] = emax2;
+    }
+    if (tid == 0) {
+      int st = 0;
+      for (int i = 0; i < m; ++i) {
+        bs[i] = st;
+        if (e[i] == 0.0) st = i + 1;
       }
-      if (H < 0) continue;
-      const int tend = H + 2 * K - 1 - L;
-      for (int rb = 0; rb < m; rb += kBlock * RPT) {
-        int row[RPT];
-        bool act[RPT];
-        T w[RPT][TS];
-        // columns are loaded PF steps before they enter the window
-        constexpr int PF = 8;
-        T pf[RPT][PF];
-#pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-          row[u] = rb + tid + u * kBlock;
-          act[u] = row[u] < m;
-#pragma unroll
-          for (int q = 0; q < TS; ++q) w[u][q] = T(0);
-          // slot 1 at t = 0 is column H+1 -> register 1
-          if (act[u]) w[u][1] = Q[(int64_t)(H + 1) * ld + row[u]];
-#pragma unroll
-          for (int q = 0; q < PF; ++q) {
-            const int col = H - q;
-            pf[u][q] = (act[u] && col >= L) ? Q[(int64_t)col * ld + row[u]] : T(0);
-          }
-        }
-        for (int t0 = 0; t0 <= tend; t0 += TS) {
-          __syncthreads();
-          for (int q = tid; q < TS * K; q += kBlock) {
-            const int ts = q / K, s = q - ts * K;
-            const int P = H - (t0 + ts) + 2 * s;
-            T c = T(1), sn = T(0);
-            if (P >= s_lo[s] && P <= s_hi[s]) {
-              const int64_t idx = (int64_t)s_off[s] + (s_hi[s] - P);
-              c = rot[2 * idx];
-              sn = rot[2 * idx + 1];
-            }
-            tab[ts][s][0] = c;
-            tab[ts][s][1] = sn;
-          }
-          __syncthreads();
-#pragma unroll
-          for (int ts = 0; ts < TS; ++ts) {
-            const int t = t0 + ts;
-            if (t <= tend) {
-              const int base = H - t;
-              // register of logical slot i at this step: (i - ts) mod TS;
-              // the column entering now was prefetched into pf[ts % PF]
-              if (base >= L) {
-#pragma unroll
-                for (int u = 0; u < RPT; ++u) w[u][(TS - ts) % TS] = pf[u][ts % PF];
-              }
-              const int cpf = base - PF;
-              if (cpf >= L) {
-#pragma unroll
-                for (int u = 0; u < RPT; ++u)
-                  if (act[u]) pf[u][ts % PF] = Q[(int64_t)cpf * ld + row[u]];
-              }
-#pragma unroll
-              for (int s = 0; s < K; ++s) {
-                const int p0 = (2 * s - ts + 2 * TS) % TS, p1 = (2 * s + 1 - ts + 2 * TS) % TS;
-                const T c = tab[ts][s][0], sn = tab[ts][s][1];
-#pragma unroll
-                for (int u = 0; u < RPT; ++u) {
-                  const T x0 = w[u][p0], x1 = w[u][p1];
-                  w[u][p1] = sn * x0 + c * x1;
-                  w[u][p0] = c * x0 - sn * x1;
-                }
-              }
-              const int pout = base + TS - 1;
-              if (pout <= H + 1 && pout >= L) {
-#pragma unroll
-                for (int u = 0; u < RPT; ++u)
-                  if (act[u]) Q[(int64_t)pout * ld + row[u]] = w[u][(TS - 1 - ts + TS) % TS];
-              }
-            }
-          }
-        }
+      int en = m;
+      for (int i = m - 1; i >= 0; --i) {
+        if (e[i] == 0.0) en = i + 1;
+        be[i] = en;
       }
     }
+    __syncthreads();
+    tn = red[0];
+    glo = red[kEigNW];
+    ghi = red[2 * kEigNW];
+    emax2 = red[3 * kEigNW];
+    for (int w = 1; w < kEigNW; ++w) {
+      tn = fmax(tn, red[w]);
+      glo = fmin(glo, red[kEigNW + w]);
+      ghi = fmax(ghi, red[2 * kEigNW + w]);
+      emax2 = fmax(emax2, red[3 * kEigNW + w]);
+    }
+    const double pivmin = kSafeMin * fmax(1.0, emax2);
+    const double pad = 2.0 * kUnitRoundoff * tn * m + 4.0 * pivmin;
+    glo -= pad;
+    ghi += pad;
+    // eigenvalues: one lane each, to a few ulps or 1e-3 eps ||T||
+    const double atol = 1e-3 * kUnitRoundoff * tn + pivmin;
+    for (int jj = tid; jj < m; jj += kEigBlock) {
+      const int s = bs[jj], t = be[jj], k = jj - s;
+      double lo = glo, hi = ghi;
+      for (int iter = 0; iter < 256; ++iter) {
+        const double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;
+        if (sturm_count(d, e2, s, t, mid, pivmin) > k) hi = mid;
+        else lo = mid;
+      }
+      lam[jj] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    // eigenvectors
+    const double ctol = a.cluster_tol * tn;
+    const double tol = kUnitRoundoff * fmax(tn, kSafeMin);
+    const double rtol = 16.0 * kUnitRoundoff * fmax(tn, kSafeMin) * m;
+    const uint64_t seed = 0x5A17B0D1ull * (uint64_t)(j + 1);
+    int ninv = 0, bad = 0;
+    for (int jj = tid; jj < m; jj += kEigBlock) {
+      const int s = bs[jj], t = be[jj];
+      const bool wp = jj > s && lam[jj] - lam[jj - 1] <= ctol;
+      const bool wn = jj + 1 < t && lam[jj + 1] - lam[jj] <= ctol;
+      double sc = 1.0;
+      if (!wp && !wn) {
+        double n2 = 0.0;
+        if (twisted_vector(d, e, s, t, lam[jj], tol, rtol, Z, U, ld, jj, n2)) {
+          sc = 1.0 / sqrt(n2);
+        } else {
+          bad += cluster_vectors(d, e, lam, s, t, jj, 1, tol, rtol, Z, U, ld, seed);
+          ++ninv;
+        }
+      } else if (!wp) {
+        int k = 1;
+        while (jj + k < t && lam[jj + k] - lam[jj + k - 1] <= ctol) ++k;
+        bad += cluster_vectors(d, e, lam, s, t, jj, k, tol, rtol, Z, U, ld, seed);
+        ninv += k;
+      }
+      e2[jj] = wp ? 1.0 : sc;  // cluster members are normalised by their leader
+    }
+    __syncthreads();
+    // normalise; zero outside the vector's block
+    for (int jj = tid; jj < m; jj += kEigBlock) {
+      const int s = bs[jj], t = be[jj];
+      const double sc = e2[jj];
+      for (int i = 0; i < m; ++i) {
+        double* zp = Z + (int64_t)i * ld + jj;
+        *zp = (i >= s && i < t) ? *zp * sc : 0.0;
+      }
+    }
+    // eigenvalues, spectrum checks and flags
+    double lmin = INFINITY, lmax = -INFINITY;
+    for (int jj = tid; jj < m; jj += kEigBlock) {
+      const double v = lam[jj];
+      lmin = fmin(lmin, v);
+      lmax = fmax(lmax, v);
+      dg[jj] = (T)v;
+    }
+    lmin = wave_min(lmin);
+    lmax = wave_max(lmax);
+    bad = (int)wave_sum((double)bad);
+    ninv = (int)wave_sum((double)ninv);
+    __syncthreads();
+    if (lane == 0) {
+      red[wv] = lmin;
+      red[kEigNW + wv] = lmax;
+      ired[wv] = bad;
+      ired[kEigNW + wv] = ninv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kEigNW; ++w) {
+        lmin = fmin(lmin, red[w]);
+        lmax = fmax(lmax, red[kEigNW + w]);
+      }
+      int nbad = 0, nin = 0;
+      for (int w = 0; w < kEigNW; ++w) {
+        nbad += ired[w];
+        nin += ired[kEigNW + w];
+      }
+      int flags = nbad ? LF_UNCONV : 0;
+      // lambda_min <= 0 has no real inverse p-th root; in the FP32 pass an
+      // estimated condition number above kappa_max sends the submatrix to
+      // the FP64 pass
+      if (!a.fp64) {
+        if ((flags & LF_UNCONV) || !(lmin > 0.0) || lmax > a.kappa_max * lmin) flags = LF_FALLBACK;
+      } else if (!(lmin > 0.0)) {
+        flags |= LF_NONPOS;
+      }
+      a.flags[it] = a.only_flagged ? (flags | LF_FALLBACK) : flags;
+      if (flags & LF_NONPOS) atomicAdd((unsigned long long*)&a.status[ST_NONPOS], 1ull);
+      if (a.fp64 && (flags & LF_UNCONV)) atomicAdd((unsigned long long*)&a.status[ST_UNCONV], 1ull);
+      if (!a.fp64 && (flags & LF_FALLBACK)) atomicAdd((unsigned long long*)&a.status[ST_FALLBACK], 1ull);
+      if (nin) atomicAdd((unsigned long long*)&a.status[ST_INVITER], (unsigned long long)nin);
+    }
+    __syncthreads();
+  }
+}
+
+// Local reorthogonalisation of the eigenvectors of T, then Z^T into Y.
+// Vectors computed one by one are orthogonal only to about eps ||T|| / gap;
+// the error lies mostly along eigenvectors of nearby eigenvalues, i.e. of
+// nearby indices. Blocks B of kOrthB consecutive vectors are made
+// orthonormal in order, against the previous (finished) block P:
+//   pass 1   C = P^T B and H = B^T B (MFMA, both from one read of P and B)
+//   small    G = H - C^T C = (B - P C)^T (B - P C), R^T R = G (Cholesky),
+//            Rinv = R^-1, D = C Rinv
+//   pass 2   B <- B Rinv - P D = (B - P C) R^-1, also stored into Y (type T)
+template <class T>
+__global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
+  __shared__ int s_item, s_bad;
+  __shared__ double acc_s[kEigNW][2][kOrthB * kOrthB];
+  __shared__ double Cs[kOrthB * kOrthB], Gs[kOrthB * kOrthB], Rs[kOrthB * kOrthB], Ri[kOrthB * kOrthB],
+      Ds[kOrthB * kOrthB];
+  typedef Mfma<double>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int li = lane & 15, lk = lane >> 4;
+  const int k = tid / kOrthB, l = tid - k * kOrthB;  // one entry of a 16 x 16 matrix
+  for (;;) {
+    const int it = next_item(a.work_ctr, &s_item);
+    if (it >= a.n_items) break;
+    if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) continue;
+    const int j = a.items[it];
+    const int m = a.rowptr[j + 1] - a.rowptr[j];
+    const int ld = a.ldm[it];
+    T* Y = at<T>(a.S, a.off[it]);
+    double* Z = at<double>(a.escr, a.eoff[it]);
+    if (tid == 0) s_bad = 0;
+    for (int j0 = 0; j0 < m; j0 += kOrthB) {
+      const int nb = (m - j0) < kOrthB ? (m - j0) : kOrthB;
+      double* B = Z + j0;
+      const double* P = Z + (j0 - kOrthB);  // used only when j0 > 0
+      const bool hasP = j0 > 0;
+      // pass 1: wave w takes rows 4w.., 4(w+NW).. (four rows per MFMA step)
+      acc_t cacc = acc_t{0, 0, 0, 0}, hacc = acc_t{0, 0, 0, 0};
+      for (int i0 = 4 * wv; i0 < m; i0 += 4 * kEigNW) {
+        const int i = i0 + lk;
+        const bool ok = i < m && li < nb;
+        const double bv = ok ? B[(int64_t)i * ld + li] : 0.0;
+        const double pv = (hasP && i < m) ? P[(int64_t)i * ld + li] : 0.0;
+        hacc = Mfma<double>::step(bv, bv, hacc);
+        cacc = Mfma<double>::step(pv, bv, cacc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = Mfma<double>::row(lk, r);
+        acc_s[wv][0][row * kOrthB + li] = cacc[r];
+        acc_s[wv][1][row * kOrthB + li] = hacc[r];
+      }
+      __syncthreads();
+      double c = 0.0, h = 0.0;
+#pragma unroll
+      for (int w = 0; w < kEigNW; ++w) {
+        c += acc_s[w][0][tid];
+        h += acc_s[w][1][tid];
+      }
+      Cs[tid] = c;
+      __syncthreads();
+      {
+        double g = h;
+        for (int q = 0; q < kOrthB; ++q) g = fma(-Cs[q * kOrthB + k], Cs[q * kOrthB + l], g);
+        if (k >= nb || l >= nb) g = (k == l) ? 1.0 : 0.0;
+        Gs[tid] = g;
+      }
+      __syncthreads();
+      // right-looking Cholesky of G: row kk of R per step
+      for (int kk = 0; kk < kOrthB; ++kk) {
+        const double piv = Gs[kk * kOrthB + kk];
+        if (tid < kOrthB) {
+          const double r = sqrt(fmax(piv, kSafeMin));
+          Rs[kk * kOrthB + tid] = tid < kk ? 0.0 : (tid == kk ? r : Gs[kk * kOrthB + tid] / r);
+        }
+        if (tid == 0 && !(piv > 0.25)) s_bad = 1;  // the vectors were far from orthonormal
+        __syncthreads();
+        if (k > kk && l > kk) Gs[tid] -= Rs[kk * kOrthB + k] * Rs[kk * kOrthB + l];
+        __syncthreads();
+      }
+      // Rinv: lane `tid` solves R x = e_tid by back substitution (its own column)
+      if (tid < kOrthB) {
+        for (int q = kOrthB - 1; q >= 0; --q) {
+          double v = (q == tid) ? 1.0 : 0.0;
+          for (int kk = q + 1; kk < kOrthB; ++kk) v = fma(-Rs[q * kOrthB + kk], Ri[kk * kOrthB + tid], v);
+          Ri[q * kOrthB + tid] = v / Rs[q * kOrthB + q];
+        }
+      }
+      __syncthreads();
+      {
+        double dv = 0.0;
+        for (int q = 0; q < kOrthB; ++q) dv = fma(Cs[k * kOrthB + q], Ri[q * kOrthB + l], dv);
+        Ds[tid] = dv;
+      }
+      __syncthreads();
+      // pass 2: thread (row, column); the 16 threads of a row sit in one
+      // wave and read the whole row before any of them writes it
+      for (int q = tid; q < m * kOrthB; q += kEigBlock) {
+        const int i = q / kOrthB, lq = q - i * kOrthB;
+        double bv[kOrthB];
+#pragma unroll
+        for (int kk = 0; kk < kOrthB; ++kk) bv[kk] = kk < nb ? B[(int64_t)i * ld + kk] : 0.0;
+        double v = 0.0;
+#pragma unroll
+        for (int kk = 0; kk < kOrthB; ++kk) v = fma(bv[kk], Ri[kk * kOrthB + lq], v);
+        if (hasP) {
+#pragma unroll
+          for (int kk = 0; kk < kOrthB; ++kk) v = fma(-P[(int64_t)i * ld + kk], Ds[kk * kOrthB + lq], v);
+        }
+        if (lq < nb) {
+          B[(int64_t)i * ld + lq] = v;
+          Y[(int64_t)i * ld + j0 + lq] = (T)v;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && s_bad) {
+      // a block without full rank: the eigensolver failed for this submatrix
+      const int fl = a.flags[it];
+      if (a.fp64) {
+        if (!(fl & LF_UNCONV)) atomicAdd((unsigned long long*)&a.status[ST_UNCONV], 1ull);
+        a.flags[it] = fl | LF_UNCONV;
+      } else if (!(fl & LF_FALLBACK)) {
+        atomicAdd((unsigned long long*)&a.status[ST_FALLBACK], 1ull);
+        a.flags[it] = LF_FALLBACK;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ back-transform
+// Q = Q1 Z on MFMA (Q1 in the W slab, Z^T = Y in the S slab).
+template <class T>
+__global__ __launch_bounds__(kBigBlock) void k_back_transform(LargeArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ int s_item;
+  T* gsm = (T*)dyn;
+  for (;;) {
+    const int it = next_item(a.work_ctr, &s_item);
+    if (it >= a.n_items) break;
+    if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) continue;
+    const int j = a.items[it];
+    const int m = a.rowptr[j + 1] - a.rowptr[j];
+    const int ld = a.ldm[it];
+    const T* Q1 = at<T>((const void*)a.W, a.off[it]);
+    const T* Y = at<T>((const void*)a.S, a.off[it]);
+    T* Q = at<T>(a.Q, a.qoff[it]);
+    wg_gemm<T, kBigNW, false, true>(m, m, m, T(1), Q1, ld, Y, ld, T(0), Q, ld, gsm);
   }
 }
 
 // ------------------------------------------------------- apply column
 // x[r] = sum_p Q[r][p] f(lambda_p) Q[c][p]; NaN when lambda_min <= 0 or the
-// QL iteration did not converge.
+// eigensolver did not converge.
 template <class T, class VT>
 __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
   extern __shared__ double dyn[];
@@ -869,49 +1093,36 @@ hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int ql_items_per_wave(int max_m, int lds_limit, int blocks_per_cu) {
-  // d and e of P submatrices in LDS (FP64), the device's LDS shared by
-  // blocks_per_cu blocks
-  const int64_t budget = ((int64_t)(lds_limit > 0 ? lds_limit : 65536) - 4096) / blocks_per_cu;
-  int p = (int)(budget / (16 * (int64_t)(max_m + 1)));
-  if (p > 64) p = 64;
-  if (p < 1) p = 1;
-  return p;
-}
+size_t eig_lds_bytes(int max_m) { return (size_t)max_m * (4 * sizeof(double) + 2 * sizeof(int)); }
 
-hipError_t launch_tridiag_ql(const LargeArgs& a0, hipStream_t s) {
-  if (a0.n_items <= 0) return hipSuccess;
-  LargeArgs a = a0;
-  a.ql_items = ql_items_per_wave(a.max_m, a.lds_limit, a.ql_bpc > 0 ? a.ql_bpc : 2);
-  const int grid = (a.n_items + a.ql_items - 1) / a.ql_items;
-  const size_t lds = (size_t)2 * a.ql_items * (a.max_m + 1) * sizeof(double);
-  if (a.fp64)
-    hipLaunchKernelGGL(k_tridiag_ql<double>, dim3(grid), dim3(64), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_tridiag_ql<float>, dim3(grid), dim3(64), lds, s, a);
-  return hipGetLastError();
-}
-
-template <class T>
-static void launch_rot_t(const LargeArgs& a, hipStream_t s) {
-  const bool two = a.max_m > kBlock;
-  if (a.rot_batch >= 16) {
-    if (two) hipLaunchKernelGGL((k_apply_rotations<T, 16, 2>), dim3(a.grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_apply_rotations<T, 16, 1>), dim3(a.grid), dim3(kBlock), 0, s, a);
-  } else {
-    if (two) hipLaunchKernelGGL((k_apply_rotations<T, 8, 2>), dim3(a.grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_apply_rotations<T, 8, 1>), dim3(a.grid), dim3(kBlock), 0, s, a);
-  }
-}
-
-hipError_t launch_apply_rotations(const LargeArgs& a, hipStream_t s) {
+hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  if (a.fp64) launch_rot_t<double>(a, s);
-  else launch_rot_t<float>(a, s);
+  const size_t lds = eig_lds_bytes(a.max_m);
+  if ((int64_t)lds + 2048 > a.lds_limit) return hipErrorInvalidConfiguration;
+  if (a.fp64)
+    hipLaunchKernelGGL(k_tridiag_eig<double>, dim3(a.grid), dim3(kEigBlock), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_tridiag_eig<float>, dim3(a.grid), dim3(kEigBlock), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_check_spectrum(const LargeArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (a.fp64)
+    hipLaunchKernelGGL(k_eig_orth<double>, dim3(a.grid), dim3(kEigBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_eig_orth<float>, dim3(a.grid), dim3(kEigBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (a.fp64)
+    hipLaunchKernelGGL(k_back_transform<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
+  else
+    hipLaunchKernelGGL(k_back_transform<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;

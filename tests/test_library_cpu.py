@@ -49,13 +49,16 @@ def test_binding_covers_header():
 def test_version_strerror_options_without_gpu():
     from paper_1710_10899_amd import _lib
     _lib.load()
-    assert _lib.submat_version() == 100
+    assert _lib.submat_version() == 110
     assert _lib.submat_strerror(-3) == "diagonal entry not stored"
     assert _lib.submat_strerror(0) == "ok"
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_KAPPA_MAX) == 1e5
-    _lib.submat_set_option(_lib.SUBMAT_OPT_ROT_BATCH, 8)
-    assert _lib.submat_get_option(_lib.SUBMAT_OPT_ROT_BATCH) == 8
-    _lib.submat_set_option(_lib.SUBMAT_OPT_ROT_BATCH, 16)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL) == 1e-5
+    _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 0.5)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL) == 0.5
+    _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-5)
+    with pytest.raises(_lib.SubmatError):
+        _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1.0)
     with pytest.raises(_lib.SubmatError):
         _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, 0.5)
     with pytest.raises(_lib.SubmatError):
@@ -87,3 +90,23 @@ def test_product_path_does_not_touch_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.replace("no CPU fallback", ""), f
+
+
+def test_tuning_table_option(tmp_path, monkeypatch):
+    from paper_1710_10899_amd import _lib
+    from paper_1710_10899_amd import autotune
+    _lib.load()
+    path = tmp_path / "tune.txt"
+    table = autotune.table_with(autotune.DEFAULTS, 1, 1024, 3)
+    assert (1, 1024, 3) in table and (1, 1024, 2) not in table
+    autotune.write_table(path, table)
+    monkeypatch.setenv("SUBMAT_TUNE_FILE", str(path))
+    _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_TUNE_FILE) == 1.0
+    _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 0)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_TUNE_FILE) == 0.0
+    with pytest.raises(_lib.SubmatError):
+        _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 2)
+    path.write_text("garbage\n")
+    _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_TUNE_FILE) == 0.0

@@ -84,12 +84,15 @@ __device__ __forceinline__ int find_sorted(const int* r, int m, int key) {
   return (m > 0 && r[lo] == key) ? lo : -1;
 }
 
-// Persistent-kernel work distribution: next item index for the block.
+// Persistent-kernel work distribution: next item index for the block. The
+// value is the same in every lane; readfirstlane lets the compiler keep it,
+// and everything derived from it (sizes, offsets, slab pointers), in scalar
+// registers.
 __device__ __forceinline__ int next_item(int* ctr, int* s_slot) {
   __syncthreads();
   if (threadIdx.x == 0) *s_slot = atomicAdd(ctr, 1);
   __syncthreads();
-  return *s_slot;
+  return __builtin_amdgcn_readfirstlane(*s_slot);
 }
 
 template <class T>

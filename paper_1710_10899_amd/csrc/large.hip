@@ -86,16 +86,21 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
 }
 
 // ------------------------------------------------------- symmetric matvec
+// The reduction runs with 8-wave workgroups (measured faster than two 4-wave
+// workgroups per compute unit: the symv's streaming rate per item decides).
+constexpr int kRedNW = 8;
+constexpr int kRedBlock = kRedNW * kWave;
 // y = A v for a symmetric n x n matrix given by its lower triangle (column
 // major, leading dimension ld), v and y in LDS, called by the whole
-// 512-thread workgroup. The columns are cut into strips of kStrip; wave w
+// workgroup. The columns are cut into strips of kStrip; wave w
 // takes strips w, 2*NW-1-w, 2*NW+w, ... (balanced over the triangle). For a
 // strip the lanes run down the rows r >= c0 in groups of 64; each lane loads
 // kStrip elements of its row (one coalesced column segment per load) and
 //   * adds sum_c A[r][c] v[c] to its wave's row partial spart[w][r];
 //   * accumulates A[r][c] v[r] (r > c) for each of the strip's columns,
 //     reduced across the wave at the end of the strip.
-// y = sum over waves of the partials, in a fixed order (deterministic).
+// After a barrier, y = sum over waves of the partials, in a fixed order
+// (deterministic), is formed by the caller.
 constexpr int kStrip = 8;
 
 // Column-dot reduction of a strip: 64 lanes each hold kStrip partials. Lane
@@ -123,34 +128,41 @@ __device__ __forceinline__ double wave_strip_sum(double (&x)[kStrip]) {
 }
 
 template <class T>
-__device__ void symv_lower(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
-                           double* y, double* spart, int max_m) {
+__device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
+                                  double* spart, int max_m) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int pl = strip_perm(lane);
   double* my = spart + (int64_t)wv * max_m;
   for (int r = lane; r < n; r += kWave) my[r] = 0.0;
   const int nstrip = (n + kStrip - 1) / kStrip;
   for (int t = 0;; ++t) {
-    const int s = t * kBigNW + ((t & 1) ? (kBigNW - 1 - wv) : wv);
+    const int s = t * kRedNW + ((t & 1) ? (kRedNW - 1 - wv) : wv);
     if (s >= nstrip) break;
     const int c0 = s * kStrip;
     double vc[kStrip], cd[kStrip];
-    const T* col[kStrip];
+    int col[kStrip];  // element offsets of the slot columns from the uniform base A
 #pragma unroll
     for (int u = 0; u < kStrip; ++u) {
       const int c = c0 + (u ^ pl);
       vc[u] = (c < n) ? v[c] : 0.0;
       cd[u] = 0.0;
-      col[u] = A + (int64_t)(c < n ? c : c0) * ld;
+      col[u] = (c < n ? c : c0) * ld;
     }
-    for (int r = c0 + lane; r - lane < n; r += kWave) {
-      const bool in = r < n;
-      double av[kStrip];
+    // two groups of 64 rows per iteration: 2 * kStrip loads in flight
+    for (int r = c0 + lane; r - lane < n; r += 2 * kWave) {
+      const int r2 = r + kWave;
+      const bool in = r < n, in2 = r2 < n;
+      double av[kStrip], aw[kStrip];
 #pragma unroll
-      for (int u = 0; u < kStrip; ++u) av[u] = (in && c0 + (u ^ pl) < n) ? (double)col[u][r] : 0.0;
+      for (int u = 0; u < kStrip; ++u) {
+        const bool cok = c0 + (u ^ pl) < n;
+        av[u] = (in && cok) ? (double)A[(uint32_t)(col[u] + r)] : 0.0;
+        aw[u] = (in2 && cok) ? (double)A[(uint32_t)(col[u] + r2)] : 0.0;
+      }
       const double vr = in ? v[r] : 0.0;
-      double racc = 0.0;
-      if (r - lane >= c0 + kStrip) {  // the whole group lies below the diagonal block
+      const double vr2 = in2 ? v[r2] : 0.0;
+      double racc = 0.0, racc2 = 0.0;
+      if (r - lane >= c0 + kStrip) {  // the whole first group lies below the diagonal block
 #pragma unroll
         for (int u = 0; u < kStrip; ++u) {
           racc = fma(av[u], vc[u], racc);
@@ -165,43 +177,114 @@ __device__ void symv_lower(const T* __restrict__ A, int ld, int n, const double*
           cd[u] = fma((r > c) ? a_ : 0.0, vr, cd[u]);
         }
       }
+      // the second group starts 64 rows lower, below the diagonal block
+#pragma unroll
+      for (int u = 0; u < kStrip; ++u) {
+        racc2 = fma(aw[u], vc[u], racc2);
+        cd[u] = fma(aw[u], vr2, cd[u]);
+      }
       if (in) my[r] += racc;
+      if (in2) my[r2] += racc2;
     }
     const double tot = wave_strip_sum(cd);
     if ((lane & (kWave / kStrip - 1)) == 0 && c0 + pl < n) my[c0 + pl] += tot;
   }
-  __syncthreads();
-  // y may alias row 0 of spart: each thread reads and writes only its own r
-  for (int r = tid; r < n; r += kBigBlock) {
-    double acc = spart[r];
+}
+
+// acc - sum_{c<i} (P[c*ld] a[c] + Q[c*ld] b[c]) with eight loads in flight
+// (P, Q: the same row of two column-major panels).
+template <class T>
+__device__ __forceinline__ double panel_correct(const T* __restrict__ P, const T* __restrict__ Q, int ld,
+                                                const double* a, const double* b, int i, double acc) {
+  double acc1 = 0.0;
+  int c = 0;
+  for (; c + 4 <= i; c += 4) {
+    double p[4], q[4];
 #pragma unroll
-    for (int w = 1; w < kBigNW; ++w) acc += spart[(int64_t)w * max_m + r];
-    y[r] = acc;
+    for (int u = 0; u < 4; ++u) {
+      p[u] = (double)P[(int64_t)(c + u) * ld];
+      q[u] = (double)Q[(int64_t)(c + u) * ld];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc = fma(-p[u], a[c + u], acc);
+      acc1 = fma(-q[u], b[c + u], acc1);
+    }
   }
+  for (; c < i; ++c) {
+    acc = fma(-(double)P[(int64_t)c * ld], a[c], acc);
+    acc1 = fma(-(double)Q[(int64_t)c * ld], b[c], acc1);
+  }
+  return acc + acc1;
 }
 
 // ------------------------------------------------------- tridiagonalise
-// Blocked Householder reduction (lower form), panel width NB. Within a
-// panel, column k = k0 + i is first brought up to date with the panel's
-// earlier vectors (A[k:, k] -= V W[k,:]^T + W V[k,:]^T), its reflector
-// (v, tau, beta) is formed, and w = tau (A22 v - V (W^T v) - W (V^T v)),
-// w -= (tau/2)(w.v) v, where A22 is the trailing matrix as it stood at the
-// start of the panel. After the panel, A22 -= V W^T + W V^T on MFMA over
-// the tiles that meet the lower triangle; only the lower triangle is read.
+// Blocked Householder reduction (lower form), panel width NB; V (the
+// Householder vectors, in S) and W (in the W slab) hold the current panel.
+// Column k = k0 + i:
+//  (2) its reflector (v, tau, beta) from the column brought up to date with
+//      the panel's earlier vectors, A[k:, k] - V W[k,:]^T - W V[k,:]^T;
+//  (3) y = A22 v with A22 the trailing matrix as it stood at the start of
+//      the panel, z1 = W^T v, z2 = V^T v, then y -= V z1 + W z2;
+//  (5) w = tau y - (tau/2)(tau y . v) v into column i of W.
+// The pass of (3) that reads the rows of V and W also brings the next
+// column up to date from the same loads (its term for v, w follows in (5)),
+// so the next reflector takes its column from LDS: one dependent global
+// round trip per column besides the symv. After the panel,
+// A22 -= V W^T + W V^T on MFMA over the tiles that meet the lower triangle;
+// only the lower triangle is ever read.
 // Outputs: d[0..m), e[0..m-1), tau[0..m-2) and v_k in column k of S.
+constexpr int kRedRows = 4;  // rows per thread in the row passes
+static_assert(kRedRows * kRedBlock >= 2048, "row passes cover the largest supported order");
+
+// y -= sum_{c<i} P[c] z1[c] + Q[c] z2[c] and an -= sum_{c<i} P[c] wr[c] +
+// Q[c] vr[c] from one set of loads (P, Q: the same row of V and W).
 template <class T>
-__global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
+__device__ __forceinline__ void panel_correct2(const T* __restrict__ P, const T* __restrict__ Q, int ld,
+                                               const double* z1, const double* z2, const double* wr,
+                                               const double* vr, int i, double& y, double& an) {
+  double y1 = 0.0, a1 = 0.0;
+  int c = 0;
+  for (; c + 4 <= i; c += 4) {
+    double p[4], q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      p[u] = (double)P[(int64_t)(c + u) * ld];
+      q[u] = (double)Q[(int64_t)(c + u) * ld];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      y = fma(-p[u], z1[c + u], y);
+      y1 = fma(-q[u], z2[c + u], y1);
+      an = fma(-p[u], wr[c + u], an);
+      a1 = fma(-q[u], vr[c + u], a1);
+    }
+  }
+  for (; c < i; ++c) {
+    const double p = (double)P[(int64_t)c * ld], q = (double)Q[(int64_t)c * ld];
+    y = fma(-p, z1[c], y);
+    y1 = fma(-q, z2[c], y1);
+    an = fma(-p, wr[c], an);
+    a1 = fma(-q, vr[c], a1);
+  }
+  y += y1;
+  an += a1;
+}
+
+template <class T>
+__global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
-  __shared__ double red[kBigNW];
+  __shared__ double red[kRedNW];
   __shared__ double vk[kNB], wk[kNB], z1[kNB], z2[kNB];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  // LDS: v, then one region shared by the symv's per-wave row partials
-  // (kBigNW rows of max_m; row 0 becomes y = A22 v) and, during the trailing
-  // update only, the GEMM staging tiles
+  // LDS: v, then one region holding the symv's per-wave row partials
+  // (kRedNW rows of max_m; row 0 becomes y = A22 v, row 1 then the next
+  // column) and, during the trailing update only, the GEMM staging tiles
   double* sv = dyn;
   double* spart = dyn + a.max_m;
   double* sy = spart;
+  double* sa = spart + a.max_m;
   T* gsm = (T*)spart;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
@@ -220,29 +303,26 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
       for (int i = 0; i < nbt; ++i) {
         const int k = k0 + i;
         const int n2 = m - k - 1;
-        // (1) bring column k (rows k..m-1) up to date with the panel's vectors
-        if (i > 0) {
-          if (tid < i) {
-            vk[tid] = (double)S[(int64_t)(k0 + tid) * ld + k];
-            wk[tid] = (double)Wb[(int64_t)tid * ld + k];
-          }
-          __syncthreads();
-          for (int r = k + tid; r < m; r += kBigBlock) {
-            double acc = (double)S[(int64_t)k * ld + r];
-#pragma unroll 1
-            for (int c = 0; c < i; ++c)
-              acc -= (double)S[(int64_t)(k0 + c) * ld + r] * wk[c] + (double)Wb[(int64_t)c * ld + r] * vk[c];
-            S[(int64_t)k * ld + r] = (T)acc;
-          }
-          __syncthreads();
+        const bool fuse_next = i + 1 < nbt;  // the next column belongs to this panel
+        // row k+1 of the panel: the next column's coefficients
+        if (fuse_next && tid < i) {
+          vk[tid] = (double)S[(int64_t)(k0 + tid) * ld + (k + 1)];
+          wk[tid] = (double)Wb[(int64_t)tid * ld + (k + 1)];
         }
-        // (2) reflector from x = A[k+1:, k]
+        // (2) reflector from x = A[k+1:, k]; the panel's first column comes
+        // from the slab (as left by the trailing update), the others from sa
         T* x = S + (int64_t)k * ld + (k + 1);
-        double part = 0.0;
-        for (int q = 1 + tid; q < n2; q += kBigBlock) part += (double)x[q] * (double)x[q];
-        const double alpha = (double)x[0];   // read before the barrier: x[0] is overwritten below
-        const double dkk = (double)S[(int64_t)k * ld + k];
-        const double sigma = block_sum<kBigNW>(part, red);
+        double part = 0.0, alpha, dkk;
+        if (i == 0) {
+          for (int q = 1 + tid; q < n2; q += kRedBlock) part += (double)x[q] * (double)x[q];
+          alpha = (double)x[0];  // read before the barrier: x[0] is overwritten below
+          dkk = (double)S[(int64_t)k * ld + k];
+        } else {
+          for (int q = 1 + tid; q < n2; q += kRedBlock) part += sa[q + 1] * sa[q + 1];
+          alpha = sa[1];
+          dkk = sa[0];
+        }
+        const double sigma = block_sum<kRedNW>(part, red);
         double beta, tk, scale;
         if (sigma == 0.0) {
           beta = alpha; tk = 0.0; scale = 0.0;
@@ -252,8 +332,9 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
           tk = (beta - alpha) / beta;
           scale = 1.0 / (alpha - beta);
         }
-        for (int q = tid; q < n2; q += kBigBlock) {
-          const double vq = (q == 0) ? 1.0 : (double)x[q] * scale;
+        for (int q = tid; q < n2; q += kRedBlock) {
+          const double xq = (i == 0) ? (double)x[q] : sa[q + 1];
+          const double vq = (q == 0) ? 1.0 : xq * scale;
           sv[q] = vq;
           x[q] = (T)vq;
         }
@@ -264,47 +345,78 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         }
         __syncthreads();
         // column k above row k+1 becomes the zero part of v_k
-        for (int q = tid; q <= k; q += kBigBlock) S[(int64_t)k * ld + q] = T(0);
-        // (3) y = A22 v, A22 = the trailing matrix as it stood at the start
-        // of the panel, lower triangle only: every element is read once and
-        // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r].
-        symv_lower(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, sy, spart, a.max_m);
-        __syncthreads();
-        // (4) y -= V (W^T v) + W (V^T v) over the panel's earlier vectors
-        if (i > 0) {
-          for (int c = wv; c < i; c += kBigNW) {
-            const T* vc = S + (int64_t)(k0 + c) * ld + (k + 1);
-            const T* wc = Wb + (int64_t)c * ld + (k + 1);
-            double p1 = 0.0, p2 = 0.0;
-#pragma unroll 1
-            for (int r = lane; r < n2; r += kWave) {
-              p1 = fma((double)wc[r], sv[r], p1);
-              p2 = fma((double)vc[r], sv[r], p2);
-            }
-            p1 = wave_sum(p1);
-            p2 = wave_sum(p2);
-            if (lane == 0) {
-              z1[c] = p1;
-              z2[c] = p2;
-            }
+        for (int q = tid; q <= k; q += kRedBlock) S[(int64_t)k * ld + q] = T(0);
+        // (3) y = A22 v, lower triangle only: every element is read once and
+        // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r]. The
+        // waves then form the panel dots z1 = W^T v, z2 = V^T v (a wave per
+        // panel column).
+        symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m);
+        for (int c = wv; c < i; c += kRedNW) {
+          const T* vc = S + (int64_t)(k0 + c) * ld + (k + 1);
+          const T* wc = Wb + (int64_t)c * ld + (k + 1);
+          double p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
+          int r = lane;
+          for (; r + kWave < n2; r += 2 * kWave) {
+            const double w0 = (double)wc[r], w1 = (double)wc[r + kWave];
+            const double v0 = (double)vc[r], v1 = (double)vc[r + kWave];
+            p1 = fma(w0, sv[r], p1);
+            p3 = fma(w1, sv[r + kWave], p3);
+            p2 = fma(v0, sv[r], p2);
+            p4 = fma(v1, sv[r + kWave], p4);
           }
-          __syncthreads();
-          for (int r = tid; r < n2; r += kBigBlock) {
-            double acc = sy[r];
-#pragma unroll 1
-            for (int c = 0; c < i; ++c)
-              acc -= (double)S[(int64_t)(k0 + c) * ld + (k + 1 + r)] * z1[c] +
-                     (double)Wb[(int64_t)c * ld + (k + 1 + r)] * z2[c];
+          if (r < n2) {
+            p1 = fma((double)wc[r], sv[r], p1);
+            p2 = fma((double)vc[r], sv[r], p2);
+          }
+          p1 = wave_sum(p1 + p3);
+          p2 = wave_sum(p2 + p4);
+          if (lane == 0) {
+            z1[c] = p1;
+            z2[c] = p2;
+          }
+        }
+        __syncthreads();
+        // each thread sums its rows' partials (fixed order), applies
+        // y -= V z1 + W z2 and, from the same loads, the next column's
+        // update by the panel's earlier vectors. sy aliases row 0 of spart
+        // and every thread reads and writes only its own rows.
+        double an[kRedRows];
+#pragma unroll
+        for (int rr = 0; rr < kRedRows; ++rr) {
+          const int r = tid + rr * kRedBlock;
+          an[rr] = 0.0;
+          if (r < n2) {
+            double acc = spart[r];
+#pragma unroll
+            for (int w = 1; w < kRedNW; ++w) acc += spart[(int64_t)w * a.max_m + r];
+            if (fuse_next) {
+              double nx = (double)S[(int64_t)(k + 1) * ld + (k + 1 + r)];
+              if (i > 0)
+                panel_correct2(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, wk, vk, i, acc,
+                               nx);
+              an[rr] = nx;
+            } else if (i > 0) {
+              acc = panel_correct(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, i, acc);
+            }
             sy[r] = acc;
           }
-          __syncthreads();
         }
-        // (5) w = tau y - (tau/2)(tau y . v) v into column i of W
+        __syncthreads();
+        // (5) w = tau y - (tau/2)(tau y . v) v into column i of W; the next
+        // column takes the term of v_k, w_k: -v w[0] - w v[0], v[0] = 1
         double pv = 0.0;
-        for (int r = tid; r < n2; r += kBigBlock) pv = fma(tk * sy[r], sv[r], pv);
-        const double Kc = 0.5 * tk * block_sum<kBigNW>(pv, red);
-        for (int r = tid; r < n2; r += kBigBlock)
-          Wb[(int64_t)i * ld + (k + 1 + r)] = (T)(tk * sy[r] - Kc * sv[r]);
+        for (int r = tid; r < n2; r += kRedBlock) pv = fma(tk * sy[r], sv[r], pv);
+        const double Kc = 0.5 * tk * block_sum<kRedNW>(pv, red);
+        const double w0 = tk * sy[0] - Kc * sv[0];
+#pragma unroll
+        for (int rr = 0; rr < kRedRows; ++rr) {
+          const int r = tid + rr * kRedBlock;
+          if (r < n2) {
+            const double wr = tk * sy[r] - Kc * sv[r];
+            Wb[(int64_t)i * ld + (k + 1 + r)] = (T)wr;
+            if (fuse_next) sa[r] = an[rr] - sv[r] * w0 - wr;
+          }
+        }
         __syncthreads();
       }
       // trailing update A22 -= V W^T + W V^T (lower tiles)
@@ -314,8 +426,8 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
         const T* V2 = S + (int64_t)k0 * ld + c0;
         const T* W2 = Wb + c0;
         T* C = S + (int64_t)c0 * ld + c0;
-        wg_gemm<T, kBigNW, false, true, true, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
-        wg_gemm<T, kBigNW, false, true, true, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kRedNW, false, true, true, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
+        wg_gemm<T, kRedNW, false, true, true, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
       }
     }
     if (tid == 0) {
@@ -329,7 +441,7 @@ __global__ __launch_bounds__(kBigBlock) void k_tridiagonalise(LargeArgs a) {
     }
     __syncthreads();
     // the last two columns carry no reflector: zero them
-    for (int q = tid; q < 2 * m; q += kBigBlock) {
+    for (int q = tid; q < 2 * m; q += kRedBlock) {
       const int c = q < m ? m - 2 : m - 1;
       const int r = q < m ? q : q - m;
       if (c >= 0) S[(int64_t)c * ld + r] = T(0);
@@ -1072,9 +1184,9 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
 
 template <class T>
 static void launch_tridiag_t(const LargeArgs& a, hipStream_t s) {
-  const size_t part = vec_lds(a, kBigNW, 8), gemm = gemm_lds_elems<kBigNW>() * sizeof(T);
+  const size_t part = vec_lds(a, kRedNW, 8), gemm = gemm_lds_elems<kRedNW>() * sizeof(T);
   const size_t lds = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
-  hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kBigBlock), lds, s, a);
+  hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kRedBlock), lds, s, a);
 }
 
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {

@@ -172,4 +172,103 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
   __syncthreads();
 }
 
+
+// Symmetric rank-2K update of the lower tiles of C (column-major, ldc):
+//   C += alpha (V W^T + W V^T),  V, W: M x K column-major (ldv, ldw),
+// as one product with inner dimension 2K (k-tiles of [V | W] against
+// [W | V]), so that C is read and written once. Tiles entirely above the
+// diagonal are skipped. Must be called by every thread of the workgroup.
+template <class T, int NW>
+__device__ void wg_syr2k_lower(int M, int K, T alpha, const T* __restrict__ V, int ldv, const T* __restrict__ W,
+                               int ldw, T* __restrict__ C, int ldc, T* smem) {
+  constexpr int BM = kGemmBM, BK = kGemmBK, BN = 16 * NW, NT = NW * kWave;
+  constexpr int AL = BM * BK / NT, BL = BN * BK / NT;
+  typedef typename Mfma<T>::acc_t acc_t;
+  // both operand tiles are contiguous along i / j: k-major LDS layout
+  constexpr int SA = BM + kGemmPad, SB = BN + kGemmPad;
+  T* As = smem;
+  T* Bs = smem + tile_elems<BM>();
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wv = tid / kWave;
+  const int wr = wv & 1, wc = wv >> 1;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nk1 = (K + BK - 1) / BK;  // k-tiles per half
+  for (int i0 = 0; i0 < M; i0 += BM) {
+    for (int j0 = 0; j0 < M; j0 += BN) {
+      if (j0 >= i0 + BM) continue;
+      acc_t acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+      // the next k-tile is fetched into registers while the current one is
+      // multiplied; first half: V against W, second half: W against V
+      T ra[AL], rb[BL];
+      auto fetch = [&](int kt) {
+        const bool second = kt >= nk1;
+        const int k0 = (second ? kt - nk1 : kt) * BK;
+        const T* Asrc = second ? W : V;
+        const T* Bsrc = second ? V : W;
+        const int lda = second ? ldw : ldv, ldb = second ? ldv : ldw;
+#pragma unroll
+        for (int e = 0; e < AL; ++e) {
+          const int q = tid + e * NT, kq = q / BM, iq = q - kq * BM;
+          const int gi = i0 + iq, gk = k0 + kq;
+          ra[e] = (gi < M && gk < K) ? Asrc[(int64_t)gk * lda + gi] : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+          const int q = tid + e * NT, kq = q / BN, jq = q - kq * BN;
+          const int gj = j0 + jq, gk = k0 + kq;
+          rb[e] = (gj < M && gk < K) ? Bsrc[(int64_t)gk * ldb + gj] : T(0);
+        }
+      };
+      fetch(0);
+      for (int kt = 0; kt < 2 * nk1; ++kt) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < AL; ++e) {
+          const int q = tid + e * NT, kq = q / BM, iq = q - kq * BM;
+          As[kq * SA + iq] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < BL; ++e) {
+          const int q = tid + e * NT, kq = q / BN, jq = q - kq * BN;
+          Bs[kq * SB + jq] = rb[e];
+        }
+        __syncthreads();
+        if (kt + 1 < 2 * nk1) fetch(kt + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          T av[2], bv[2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) av[a] = As[(kk + lk) * SA + wr * 32 + a * 16 + li];
+#pragma unroll
+          for (int b = 0; b < 2; ++b) bv[b] = Bs[(kk + lk) * SB + wc * 32 + b * 16 + li];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int gj = j0 + wc * 32 + b * 16 + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + wr * 32 + a * 16 + Mfma<T>::row(lk, r);
+            if (gi < M && gj < M) {
+              T* cp = C + (int64_t)gj * ldc + gi;
+              *cp = alpha * acc[a][b][r] + *cp;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace submat

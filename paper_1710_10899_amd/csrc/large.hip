@@ -127,18 +127,65 @@ __device__ __forceinline__ double wave_strip_sum(double (&x)[kStrip]) {
   return t;
 }
 
+// Column dots of strip [c0, c0 + kStrip) of a panel P (n rows, ncol
+// columns, leading dimension ld): z[c] = P[:, c]^T v, with the lane
+// partials and the reduction of the symv's strips.
+template <class T>
+__device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld, int n, int ncol, int c0,
+                                                 const double* __restrict__ v, double* z, int lane, int pl) {
+  double cd[kStrip];
+  int col[kStrip];
+#pragma unroll
+  for (int u = 0; u < kStrip; ++u) {
+    const int c = c0 + (u ^ pl);
+    cd[u] = 0.0;
+    col[u] = (c < ncol ? c : c0) * ld;
+  }
+  for (int r = lane; r - lane < n; r += 2 * kWave) {
+    const int r2 = r + kWave;
+    const bool in = r < n, in2 = r2 < n;
+    const uint32_t ra = in ? r : 0, rb = in2 ? r2 : 0;
+    double av[kStrip], aw[kStrip];
+#pragma unroll
+    for (int u = 0; u < kStrip; ++u) {
+      av[u] = (double)P[(uint32_t)col[u] + ra];
+      aw[u] = (double)P[(uint32_t)col[u] + rb];
+    }
+    const double vr = in ? v[r] : 0.0, vr2 = in2 ? v[r2] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kStrip; ++u) {
+      const bool cok = c0 + (u ^ pl) < ncol;
+      cd[u] = fma(cok ? av[u] : 0.0, vr, cd[u]);
+      cd[u] = fma(cok ? aw[u] : 0.0, vr2, cd[u]);
+    }
+  }
+  const double tot = wave_strip_sum(cd);
+  if ((lane & (kWave / kStrip - 1)) == 0 && c0 + pl < ncol) z[c0 + pl] = tot;
+}
+
+// The strips of the symv of the trailing matrix A (n x n, lower triangle)
+// and, first in the schedule, the strips of the panel dots z1 = Wp^T v and
+// z2 = Vp^T v (npc columns each, n rows, leading dimension ld).
 template <class T>
 __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
-                                  double* spart, int max_m) {
+                                  double* spart, int max_m, const T* __restrict__ Vp, const T* __restrict__ Wp,
+                                  int npc, double* z1, double* z2) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int pl = strip_perm(lane);
   double* my = spart + (int64_t)wv * max_m;
   for (int r = lane; r < n; r += kWave) my[r] = 0.0;
-  const int nstrip = (n + kStrip - 1) / kStrip;
+  const int nps = (npc + kStrip - 1) / kStrip;
+  const int nextra = 2 * nps;
+  const int nstrip = nextra + (n + kStrip - 1) / kStrip;
   for (int t = 0;; ++t) {
     const int s = t * kRedNW + ((t & 1) ? (kRedNW - 1 - wv) : wv);
     if (s >= nstrip) break;
-    const int c0 = s * kStrip;
+    if (s < nextra) {
+      const bool isw = s < nps;
+      panel_strip_dots(isw ? Wp : Vp, ld, n, npc, (isw ? s : s - nps) * kStrip, v, isw ? z1 : z2, lane, pl);
+      continue;
+    }
+    const int c0 = (s - nextra) * kStrip;
     double vc[kStrip], cd[kStrip];
     int col[kStrip];  // element offsets of the slot columns from the uniform base A
 #pragma unroll
@@ -152,12 +199,21 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
     for (int r = c0 + lane; r - lane < n; r += 2 * kWave) {
       const int r2 = r + kWave;
       const bool in = r < n, in2 = r2 < n;
+      // unconditional loads (rows past the end read row 0 of a valid column,
+      // columns past the end read column c0) and masked values: no branch
+      // per load
+      const uint32_t ra = in ? r : 0, rb = in2 ? r2 : 0;
       double av[kStrip], aw[kStrip];
 #pragma unroll
       for (int u = 0; u < kStrip; ++u) {
+        av[u] = (double)A[(uint32_t)col[u] + ra];
+        aw[u] = (double)A[(uint32_t)col[u] + rb];
+      }
+#pragma unroll
+      for (int u = 0; u < kStrip; ++u) {
         const bool cok = c0 + (u ^ pl) < n;
-        av[u] = (in && cok) ? (double)A[(uint32_t)(col[u] + r)] : 0.0;
-        aw[u] = (in2 && cok) ? (double)A[(uint32_t)(col[u] + r2)] : 0.0;
+        av[u] = (in && cok) ? av[u] : 0.0;
+        aw[u] = (in2 && cok) ? aw[u] : 0.0;
       }
       const double vr = in ? v[r] : 0.0;
       const double vr2 = in2 ? v[r2] : 0.0;
@@ -347,34 +403,10 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
         // column k above row k+1 becomes the zero part of v_k
         for (int q = tid; q <= k; q += kRedBlock) S[(int64_t)k * ld + q] = T(0);
         // (3) y = A22 v, lower triangle only: every element is read once and
-        // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r]. The
-        // waves then form the panel dots z1 = W^T v, z2 = V^T v (a wave per
-        // panel column).
-        symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m);
-        for (int c = wv; c < i; c += kRedNW) {
-          const T* vc = S + (int64_t)(k0 + c) * ld + (k + 1);
-          const T* wc = Wb + (int64_t)c * ld + (k + 1);
-          double p1 = 0.0, p2 = 0.0, p3 = 0.0, p4 = 0.0;
-          int r = lane;
-          for (; r + kWave < n2; r += 2 * kWave) {
-            const double w0 = (double)wc[r], w1 = (double)wc[r + kWave];
-            const double v0 = (double)vc[r], v1 = (double)vc[r + kWave];
-            p1 = fma(w0, sv[r], p1);
-            p3 = fma(w1, sv[r + kWave], p3);
-            p2 = fma(v0, sv[r], p2);
-            p4 = fma(v1, sv[r + kWave], p4);
-          }
-          if (r < n2) {
-            p1 = fma((double)wc[r], sv[r], p1);
-            p2 = fma((double)vc[r], sv[r], p2);
-          }
-          p1 = wave_sum(p1 + p3);
-          p2 = wave_sum(p2 + p4);
-          if (lane == 0) {
-            z1[c] = p1;
-            z2[c] = p2;
-          }
-        }
+        // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r]; the
+        // panel dots z1 = W^T v, z2 = V^T v run as extra strips.
+        symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m,
+                          S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2);
         __syncthreads();
         // each thread sums its rows' partials (fixed order), applies
         // y -= V z1 + W z2 and, from the same loads, the next column's
@@ -426,8 +458,7 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
         const T* V2 = S + (int64_t)k0 * ld + c0;
         const T* W2 = Wb + c0;
         T* C = S + (int64_t)c0 * ld + c0;
-        wg_gemm<T, kRedNW, false, true, true, false>(M, M, nbt, T(-1), V2, ld, W2, ld, T(1), C, ld, gsm);
-        wg_gemm<T, kRedNW, false, true, true, false>(M, M, nbt, T(-1), W2, ld, V2, ld, T(1), C, ld, gsm);
+        wg_syr2k_lower<T, kRedNW>(M, nbt, T(-1), V2, ld, W2, ld, C, ld, gsm);
       }
     }
     if (tid == 0) {
@@ -486,16 +517,12 @@ __global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
         const int nbt = (nref - k0) < kNB ? (nref - k0) : kNB;
         const int n2 = m - k0 - 1;
         const T* V = S + (int64_t)k0 * ld + (k0 + 1);
-        // Gram matrix of the block's vectors
+        // Gram matrix V^T V of the block's vectors on MFMA (into the start
+        // of the Wm scratch, which is written only later), then into LDS
+        wg_gemm<T, kBigNW, true, false>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Wm, nbt, gsm);
         for (int q = tid; q < nbt * nbt; q += kBigBlock) {
-          const int r = q / nbt, c = q - r * nbt;
-          double g = 0.0;
-          if (r <= c) {
-            const T* vr = V + (int64_t)r * ld;
-            const T* vc = V + (int64_t)c * ld;
-            for (int s = c; s < n2; ++s) g = fma((double)vr[s], (double)vc[s], g);
-          }
-          Gs[r * kNB + c] = g;
+          const int c = q / nbt, r = q - c * nbt;
+          Gs[r * kNB + c] = (double)Wm[(int64_t)c * nbt + r];
         }
         __syncthreads();
         if (tid < kWave) {

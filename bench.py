@@ -26,8 +26,8 @@ HBM_PEAK_GBS = 8000.0
 
 # library kernel (substring of its symbol) -> phase of submat_time_phases
 KERNEL_PHASE = {"k_small": "small-jacobi", "k_gather_large": "gather", "k_tridiagonalise": "tridiagonalise",
-                "k_form_q1": "form-q1", "k_tridiag_eig": "tridiagonal-eig", "k_eig_orth": "eig-reorthogonalise",
-                "k_back_transform": "back-transform",
+                "k_tridiag_eig": "tridiagonal-eig", "k_eig_orth": "reorthogonalise",
+                "k_apply_reflectors": "back-transform",
                 "k_apply_column": "apply-column", "k_adjoint": "adjoint", "k_plan_pattern": "plan-reset"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 CSRC = os.path.join(ROOT, "paper_1710_10899_amd", "csrc")
@@ -38,11 +38,12 @@ def log(msg: str) -> None:
 
 
 def flops_model(m):
-    """Algorithmic flops per column: forward (14/3)m^3 + 3m^2 (tridiagonal
-    reduction 4/3, forming Q1 4/3, Q = Q1 Z 2, then f and the column),
-    adjoint 3m^3 + 5m^2 (Q M and the symmetric product with Q^T)."""
+    """Algorithmic flops per column: forward (10/3)m^3 + 3m^2 (tridiagonal
+    reduction 4/3, applying the reflectors to the eigenvectors of T 2, then
+    f and the column), adjoint 3m^3 + 5m^2 (Q M and the symmetric product
+    with Q^T)."""
     m = m.astype("float64")
-    return float(((14.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
+    return float(((10.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
 
 
 def phase_work(m, phase):
@@ -53,8 +54,6 @@ def phase_work(m, phase):
     m = m[m > 64].astype("float64")
     if phase == "tridiagonalise":
         return float((4.0 / 3.0) * (m ** 3).sum()), "byte", "hbm"
-    if phase == "form-q1":
-        return float((4.0 / 3.0) * (m ** 3).sum()), "flop", "mfma"
     if phase == "back-transform":
         return float(2.0 * (m ** 3).sum()), "flop", "mfma"
     if phase == "adjoint":

@@ -169,8 +169,8 @@ int32_t submat_version(void);
  * with direct launches on `stream`, times each phase with HIP events recorded on
  * that stream, and writes per-phase totals in milliseconds to phase_ms[] and the
  * number of launches to phase_launches[] (arrays of SUBMAT_NUM_PHASES entries).
- * Phase order: plan-reset, small-jacobi, gather, tridiagonalise, form-q1,
- * tridiagonal-eig, back-transform, apply-column, adjoint, fallback.
+ * Phase order: plan-reset, small-jacobi, gather, tridiagonalise, tridiagonal-eig,
+ * reorthogonalise, back-transform, apply-column, adjoint, fallback.
  */
 #define SUBMAT_NUM_PHASES 10
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals,

@@ -37,7 +37,7 @@ SUBMAT_OPT_CLUSTER_TOL = 5
 SUBMAT_OPT_TUNE_FILE = 6
 SUBMAT_NUM_PHASES = 10
 
-PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "form-q1", "tridiagonal-eig",
+PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "tridiagonal-eig", "reorthogonalise",
           "back-transform", "apply-column", "adjoint", "fallback"]
 
 # exported symbol -> (restype, argtypes)

@@ -29,8 +29,8 @@ DEFAULTS = [(1, 128, 8), (1, 256, 4), (1, 1024, 2), (1, 1 << 30, 1),
             (0, 128, 8), (0, 256, 4), (0, 1024, 2), (0, 1 << 30, 1),
             (2, 256, 8), (2, 512, 6), (2, 1024, 4), (2, 1 << 30, 1)]
 BUCKETS = (128, 256, 512, 1024)
-DENSE_PHASES = ("gather", "tridiagonalise", "form-q1", "back-transform", "apply-column", "adjoint")
-EIG_PHASES = ("tridiagonal-eig",)
+DENSE_PHASES = ("gather", "tridiagonalise", "back-transform", "apply-column", "adjoint")
+EIG_PHASES = ("tridiagonal-eig", "reorthogonalise")
 
 
 def write_table(path, table):

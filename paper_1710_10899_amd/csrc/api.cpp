@@ -84,6 +84,13 @@ int get_ctx(DeviceCtx** out) {
 }
 
 // --------------------------------------------------------------------- plan
+// Scratch bytes per large item: the eigensolver's two FP64 ld x ld arrays,
+// or the back-transformation's blocks (sized in FP64 for both precisions).
+int64_t scratch_bytes(int ld) {
+  const int64_t eig = 2 * (int64_t)ld * ld, back = (int64_t)apply_scratch_elems(ld);
+  return 8 * (eig > back ? eig : back);
+}
+
 struct Chunk {
   int start = 0, count = 0, max_m = 0;
   int64_t slab_bytes = 0;   // S (and Q, W) bytes for this chunk
@@ -190,12 +197,13 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   double budget = g_opt.ws_bytes > 0 ? g_opt.ws_bytes : 0.5 * (double)free_b;
-  // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), eigensolver scratch 16 ld^2
+  // per item: S, Q, W slabs (8 ld^2 each), 4 vectors (8 ld each), scratch of the eigensolver (two FP64
+  // ld^2 arrays) and of the back-transformation
   int64_t sq = 0, sd = 0;
   Chunk cur;
   auto item_bytes = [&](int m, int ld) {
     (void)m;
-    return 5 * 8 * (int64_t)ld * ld + 4 * 8 * (int64_t)ld;
+    return 3 * 8 * (int64_t)ld * ld + 4 * 8 * (int64_t)ld + scratch_bytes(ld);
   };
   double used = 0;
   for (int g = 0; g < nl; ++g) {
@@ -214,7 +222,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
     eoff[g] = cur.escr_bytes;
     cur.slab_bytes += 8 * (int64_t)ld * ld;
     cur.vec_bytes += 8 * (int64_t)ld;
-    cur.escr_bytes += 16 * (int64_t)ld * ld;
+    cur.escr_bytes += scratch_bytes(ld);
     cur.max_m = std::max(cur.max_m, m);
     cur.count++;
     used += ib;
@@ -269,7 +277,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
 }
 
 // ----------------------------------------------------------- launch sequence
-enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_FORMQ1, PH_EIG, PH_BACK, PH_COLUMN, PH_ADJOINT, PH_FALLBACK, PH_N };
+enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_EIG, PH_ORTH, PH_BACK, PH_COLUMN, PH_ADJOINT, PH_FALLBACK, PH_N };
 
 struct Call {
   const void* vals;
@@ -384,7 +392,6 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
   if (eig) {
     next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(a, s));
     next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(a, s));
-    next(); HIP_SEQ(ph < 0 ? PH_FORMQ1 : ph, launch_form_q1(a, s));
     {
       // the eigensolver's workgroups share a compute unit's LDS
       LargeArgs b = a;
@@ -395,7 +402,7 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
       b.work_ctr = a.work_ctr;
       HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_tridiag_eig(b, s));
     }
-    next(); HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_eig_orth(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_ORTH : ph, launch_eig_orth(a, s));
     next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(a, s));
   }
   next();

@@ -5,8 +5,8 @@
 //
 //   C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C
 //
-// All matrices column-major in global memory (L2-resident slabs). The
-// workgroup (NW waves) walks C in BM x BN tiles, BM = 64, BN = 16 * NW;
+// All matrices column-major in global memory. The workgroup (NW waves)
+// walks C in BM x BN tiles, BM = 64, BN = 16 * NW;
 // wave w owns the 32 x 32 block (w % 2, w / 2) of the tile as 2 x 2 MFMA
 // output tiles. Operand tiles of depth BK = 16 are staged through LDS,
 // k-major, so that every lane reads its MFMA operand without bank
@@ -65,13 +65,16 @@ template <int NW> constexpr int gemm_lds_elems() { return tile_elems<kGemmBM>() 
 // LOWER: tiles lying entirely above the diagonal of C are skipped (for
 // symmetric results kept in the lower triangle).
 // Must be called by every thread of the workgroup (contains barriers).
-// PREFETCH: the next k-tile is fetched into registers while the current one
-// is multiplied (costs 6-8 registers; off where registers are scarce).
-template <class T, int NW, bool TA, bool TB, bool LOWER = false, bool PREFETCH = true>
+// PF: k-tiles fetched ahead into registers while the current one is
+// multiplied (0, 1 or 2; each costs 6-8 registers). Two tiles in flight
+// cover the HBM latency, which exceeds the MFMA time of one 16-deep k-tile.
+template <class T, int NW, bool TA, bool TB, bool LOWER = false, int PF = 1>
 __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, int lda,
                         const T* __restrict__ B, int ldb, T beta, T* __restrict__ C, int ldc, T* smem) {
+  static_assert(PF >= 0 && PF <= 2, "prefetch depth 0..2");
   constexpr int BM = kGemmBM, BK = kGemmBK, BN = 16 * NW, NT = NW * kWave;
   constexpr int AL = BM * BK / NT, BL = BN * BK / NT;  // tile elements per thread
+  constexpr int NS = PF > 1 ? PF : 1;                  // register slots
   typedef typename Mfma<T>::acc_t acc_t;
   // A tile: k-major unless A is transposed (then contiguous along k);
   // B tile: k-major if B is transposed (contiguous along j), else k-minor.
@@ -81,7 +84,11 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
   T* Bs = smem + tile_elems<BM>();
   auto a_at = [&](int kq, int iq) -> T& { return TA ? As[iq * SA + kq] : As[kq * SA + iq]; };
   auto b_at = [&](int kq, int jq) -> T& { return TB ? Bs[kq * SB + jq] : Bs[jq * SB + kq]; };
-  const int tid = threadIdx.x;
+  // an opaque copy of the thread index keeps the compiler from hoisting this
+  // product's index arithmetic out of the caller's loops (where the
+  // hoisted values of several products would stay live at once)
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int wr = wv & 1, wc = wv >> 1;
   const int li = lane & 15, lk = lane >> 4;
@@ -101,43 +108,42 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-      // the next k-tile is fetched into registers while the current one is
-      // multiplied from LDS
-      T ra[AL], rb[BL];
-      auto fetch = [&](int k0) {
+      T ra[NS][AL], rb[NS][BL];
+      auto fetch = [&](int slot, int k0) {
 #pragma unroll
         for (int e = 0; e < AL; ++e) {
           int kq, iq;
           a_pos(tid + e * NT, kq, iq);
           const int gi = i0 + iq, gk = k0 + kq;
-          ra[e] = (gi < M && gk < K) ? (TA ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi]) : T(0);
+          ra[slot][e] = (gi < M && gk < K) ? (TA ? A[(int64_t)gi * lda + gk] : A[(int64_t)gk * lda + gi]) : T(0);
         }
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
           int kq, jq;
           b_pos(tid + e * NT, kq, jq);
           const int gj = j0 + jq, gk = k0 + kq;
-          rb[e] = (gj < N && gk < K) ? (TB ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk]) : T(0);
+          rb[slot][e] = (gj < N && gk < K) ? (TB ? B[(int64_t)gk * ldb + gj] : B[(int64_t)gj * ldb + gk]) : T(0);
         }
       };
-      if (PREFETCH) fetch(0);
-      for (int k0 = 0; k0 < K; k0 += BK) {
-        if (!PREFETCH) fetch(k0);
+      // one k-tile: registers of `slot` into LDS, then (after refilling the
+      // slot with tile k0 + PF*BK) its MFMAs
+      auto step = [&](int slot, int k0) {
+        if (PF == 0) fetch(0, k0);
         __syncthreads();
 #pragma unroll
         for (int e = 0; e < AL; ++e) {
           int kq, iq;
           a_pos(tid + e * NT, kq, iq);
-          a_at(kq, iq) = ra[e];
+          a_at(kq, iq) = ra[slot][e];
         }
 #pragma unroll
         for (int e = 0; e < BL; ++e) {
           int kq, jq;
           b_pos(tid + e * NT, kq, jq);
-          b_at(kq, jq) = rb[e];
+          b_at(kq, jq) = rb[slot][e];
         }
         __syncthreads();
-        if (PREFETCH && k0 + BK < K) fetch(k0 + BK);
+        if (PF > 0 && k0 + PF * BK < K) fetch(slot, k0 + PF * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
           T av[2], bv[2];
@@ -150,6 +156,16 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
 #pragma unroll
             for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
         }
+      };
+      if (PF >= 1) fetch(0, 0);
+      if (PF >= 2 && BK < K) fetch(NS - 1, BK);
+      if (PF >= 2) {
+        for (int k0 = 0; k0 < K; k0 += 2 * BK) {
+          step(0, k0);
+          if (k0 + BK < K) step(NS - 1, k0 + BK);
+        }
+      } else {
+        for (int k0 = 0; k0 < K; k0 += BK) step(0, k0);
       }
       // epilogue
 #pragma unroll
@@ -172,7 +188,6 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
   __syncthreads();
 }
 
-
 // Symmetric rank-2K update of the lower tiles of C (column-major, ldc):
 //   C += alpha (V W^T + W V^T),  V, W: M x K column-major (ldv, ldw),
 // as one product with inner dimension 2K (k-tiles of [V | W] against
@@ -188,7 +203,8 @@ __device__ void wg_syr2k_lower(int M, int K, T alpha, const T* __restrict__ V, i
   constexpr int SA = BM + kGemmPad, SB = BN + kGemmPad;
   T* As = smem;
   T* Bs = smem + tile_elems<BM>();
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));  // see wg_gemm
   const int lane = tid & (kWave - 1), wv = tid / kWave;
   const int wr = wv & 1, wc = wv >> 1;
   const int li = lane & 15, lk = lane >> 4;

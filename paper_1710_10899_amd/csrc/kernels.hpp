@@ -68,16 +68,16 @@ struct LargeArgs {
   const int64_t* qoff;    // per item: Q slab offset (workspace or saved buffer)
   const int64_t* voff;    // per item: offset of its e / tau vectors
   const int64_t* doff;    // per item: offset of d (eigenvalues after the eigensolver)
-  const int64_t* eoff;    // per item: offset of its eigensolver scratch (2 ld^2 doubles)
+  const int64_t* eoff;    // per item: offset of its scratch (eigensolver, back-transformation)
   int n_items;
   int max_m;
-  void* S;                // slab base (Householder vectors, then Z^T)
-  void* Q;                // slab base (eigenvectors)
-  void* W;                // slab base (Q1, adjoint scratch)
+  void* S;                // slab base (gathered S_j, then the Householder vectors)
+  void* Q;                // slab base (Z, then the eigenvectors Q1 Z)
+  void* W;                // slab base (panel W of the reduction, adjoint scratch)
   void* d;                // per item vectors (eigenvalues after the eigensolver)
   void* e;
   void* tau;
-  void* escr;             // eigensolver scratch
+  void* escr;             // scratch of the eigensolver and the back-transformation
   int32_t* flags;         // per item: bit0 nonpositive, bit1 fallback, bit2 unconverged
   int p;
   double kappa_max;
@@ -96,11 +96,11 @@ enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
-hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);
 hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s);
 hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s);
 size_t eig_lds_bytes(int max_m);
+size_t apply_scratch_elems(int ld);  // scratch elements per item of the back-transformation
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s);
 

@@ -4,12 +4,12 @@
 //   tridiag     blocked Householder reduction S = Q1 T Q1^T (lower form): per
 //               panel of NB columns a lower-triangle symv per column, and one
 //               rank-2*NB trailing update on MFMA
-//   form_q1     Q1 accumulated explicitly from compact-WY blocks of NB
-//               reflectors, products on MFMA (into the W slab)
 //   eig         T = Z diag(lambda) Z^T in FP64: bisection for the
 //               eigenvalues, twisted factorisation / inverse iteration for
-//               the eigenvectors (Z^T into the S slab)
-//   back        Q = Q1 Z, one m x m x m product on MFMA
+//               the eigenvectors, local reorthogonalisation (Z into the Q
+//               slab)
+//   back        Q = Q1 Z: the reflectors applied to Z in compact-WY blocks
+//               of 64, products on MFMA
 //   column      x = Q (f(lambda) o Q[c,:]^T) into X's value segment
 //               (Sections 3.3-3.4)
 //   adjoint     D = Q sym(G o (a b^T)) Q^T on MFMA, scattered into dA's
@@ -480,94 +480,6 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
   }
 }
 
-// ------------------------------------------------------------- form Q1
-// Q1 = B_0 B_1 ... with B_t = I - V_t T_t V_t^T the compact-WY form of NB
-// consecutive reflectors (T_t upper triangular: T[c][c] = tau_c,
-// T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c]). Backward accumulation
-// from the identity: Q22 -= V (T (V^T Q22)) with Q22 = Q[k0+1:, k0+1:].
-template <class T>
-__global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
-  extern __shared__ double dyn[];
-  __shared__ int s_item;
-  __shared__ double Gs[kNB * kNB], Ts[kNB * kNB];
-  const int tid = threadIdx.x;
-  T* gsm = (T*)dyn;
-  for (;;) {
-    const int it = next_item(a.work_ctr, &s_item);
-    if (it >= a.n_items) break;
-    if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) continue;
-    const int j = a.items[it];
-    const int m = a.rowptr[j + 1] - a.rowptr[j];
-    const int ld = a.ldm[it];
-    const T* S = at<T>((const void*)a.S, a.off[it]);
-    T* Q = at<T>(a.W, a.off[it]);        // Q1 is formed in the W slab
-    T* Wm = at<T>(a.escr, a.eoff[it]);   // NB x (m-1) scratch
-    const T* tau = at<T>((const void*)a.tau, a.voff[it]);
-    const int64_t tot = (int64_t)ld * ld;
-    for (int64_t q = tid; q < tot; q += kBigBlock) {
-      const int64_t c = q / ld, r = q - c * ld;
-      Q[q] = (r == c && r < m) ? T(1) : T(0);
-    }
-    __syncthreads();
-    const int nref = m - 2;
-    if (nref > 0) {
-      const int nblk = (nref + kNB - 1) / kNB;
-      for (int t = nblk - 1; t >= 0; --t) {
-        const int k0 = t * kNB;
-        const int nbt = (nref - k0) < kNB ? (nref - k0) : kNB;
-        const int n2 = m - k0 - 1;
-        const T* V = S + (int64_t)k0 * ld + (k0 + 1);
-        // Gram matrix V^T V of the block's vectors on MFMA (into the start
-        // of the Wm scratch, which is written only later), then into LDS
-        wg_gemm<T, kBigNW, true, false>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Wm, nbt, gsm);
-        for (int q = tid; q < nbt * nbt; q += kBigBlock) {
-          const int c = q / nbt, r = q - c * nbt;
-          Gs[r * kNB + c] = (double)Wm[(int64_t)c * nbt + r];
-        }
-        __syncthreads();
-        if (tid < kWave) {
-          for (int c = 0; c < nbt; ++c) {
-            const double tc = (double)tau[k0 + c];
-            // T[r][c] for r < c: -tau_c sum_{s=r}^{c-1} T[r][s] G[s][c]
-            double v = 0.0;
-            if (tid < c) {
-              for (int s = tid; s < c; ++s) v = fma(Ts[tid * kNB + s], Gs[s * kNB + c], v);
-              v = -tc * v;
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (tid < c) Ts[tid * kNB + c] = v;
-            if (tid == c) Ts[c * kNB + c] = tc;
-            if (tid > c && tid < kNB) Ts[tid * kNB + c] = 0.0;
-            __builtin_amdgcn_wave_barrier();
-          }
-        }
-        __syncthreads();
-        // Wm (nbt x n2, ld nbt) = V^T Q22
-        T* Q22 = Q + (int64_t)(k0 + 1) * ld + (k0 + 1);
-        wg_gemm<T, kBigNW, true, false>(nbt, n2, n2, T(1), V, ld, Q22, ld, T(0), Wm, nbt, gsm);
-        // Wm = T Wm, 64 columns at a time through LDS
-        for (int c0 = 0; c0 < n2; c0 += 64) {
-          const int nc = (n2 - c0) < 64 ? (n2 - c0) : 64;
-          for (int q = tid; q < nbt * nc; q += kBigBlock) {
-            const int c = q / nbt, r = q - c * nbt;
-            gsm[c * kNB + r] = Wm[(int64_t)(c0 + c) * nbt + r];
-          }
-          __syncthreads();
-          for (int q = tid; q < nbt * nc; q += kBigBlock) {
-            const int c = q / nbt, r = q - c * nbt;
-            double acc = 0.0;
-            for (int q2 = r; q2 < nbt; ++q2) acc = fma(Ts[r * kNB + q2], (double)gsm[c * kNB + q2], acc);
-            Wm[(int64_t)(c0 + c) * nbt + r] = (T)acc;
-          }
-          __syncthreads();
-        }
-        // Q22 -= V Wm
-        wg_gemm<T, kBigNW, false, false>(n2, n2, nbt, T(-1), V, ld, Wm, nbt, T(1), Q22, ld, gsm);
-      }
-    }
-  }
-}
-
 // --------------------------------------------- tridiagonal eigensolver
 // Eigen-decomposition of T = tridiag(e, d, e) in FP64 (Section 3.2 leaves
 // the dense eigensolver open; this is bisection plus inverse iteration):
@@ -584,10 +496,10 @@ __global__ __launch_bounds__(kBigBlock) void k_form_q1(LargeArgs a) {
 //    member: inverse iteration with LDL^T solves from a seeded start vector,
 //    each iterate orthogonalised (modified Gram-Schmidt) against the
 //    cluster's earlier vectors, with perturbed shifts for coincident values.
-// Eigenvalues replace d (ascending within each block); eigenvector j is
-// stored as row j of Y (Y[j][i] at i*ld + j, so a lane's stores of one
-// component coalesce across lanes) in the S slab. Two FP64 m x m scratch
-// arrays (lane j owns column j) hold the factors.
+// Eigenvalues replace d (ascending within each block). Two FP64 m x m
+// scratch arrays Z and U hold the factors, lane j owning column j (element
+// (i, j) at i*ld + j, so the lanes' accesses to one component coalesce);
+// eigenvector j ends normalised in column j of Z.
 constexpr int kEigBlock = 256;
 constexpr int kEigNW = kEigBlock / kWave;
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
@@ -932,7 +844,7 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
   }
 }
 
-// Local reorthogonalisation of the eigenvectors of T, then Z^T into Y.
+// Local reorthogonalisation of the eigenvectors of T, then Z into the Q slab.
 // Vectors computed one by one are orthogonal only to about eps ||T|| / gap;
 // the error lies mostly along eigenvectors of nearby eigenvalues, i.e. of
 // nearby indices. Blocks B of kOrthB consecutive vectors are made
@@ -940,13 +852,14 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
 //   pass 1   C = P^T B and H = B^T B (MFMA, both from one read of P and B)
 //   small    G = H - C^T C = (B - P C)^T (B - P C), R^T R = G (Cholesky),
 //            Rinv = R^-1, D = C Rinv
-//   pass 2   B <- B Rinv - P D = (B - P C) R^-1, also stored into Y (type T)
+//   pass 2   B <- B Rinv - P D = (B - P C) R^-1, also stored into Q (type T)
 template <class T>
 __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
   __shared__ int s_item, s_bad;
   __shared__ double acc_s[kEigNW][2][kOrthB * kOrthB];
   __shared__ double Cs[kOrthB * kOrthB], Gs[kOrthB * kOrthB], Rs[kOrthB * kOrthB], Ri[kOrthB * kOrthB],
       Ds[kOrthB * kOrthB];
+  __shared__ double tile[kOrthB * (kWave + 1)];
   typedef Mfma<double>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
@@ -958,7 +871,7 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
-    T* Y = at<T>(a.S, a.off[it]);
+    T* Qz = at<T>(a.Q, a.qoff[it]);  // Z, column-major, for the back-transformation
     double* Z = at<double>(a.escr, a.eoff[it]);
     if (tid == 0) s_bad = 0;
     for (int j0 = 0; j0 < m; j0 += kOrthB) {
@@ -1025,26 +938,35 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
         Ds[tid] = dv;
       }
       __syncthreads();
-      // pass 2: thread (row, column); the 16 threads of a row sit in one
-      // wave and read the whole row before any of them writes it
-      for (int q = tid; q < m * kOrthB; q += kEigBlock) {
-        const int i = q / kOrthB, lq = q - i * kOrthB;
-        double bv[kOrthB];
+      // pass 2, 64 rows at a time: thread (row, column); the 16 threads of
+      // a row sit in one wave and read the whole row before any of them
+      // writes it. The columns go to Q (column-major) through an LDS
+      // transpose so that both the reads and the writes coalesce.
+      for (int i0 = 0; i0 < m; i0 += kWave) {
+        for (int q = tid; q < kWave * kOrthB; q += kEigBlock) {
+          const int ii = q / kOrthB, lq = q - ii * kOrthB, i = i0 + ii;
+          double v = 0.0;
+          if (i < m) {
+            double bv[kOrthB];
 #pragma unroll
-        for (int kk = 0; kk < kOrthB; ++kk) bv[kk] = kk < nb ? B[(int64_t)i * ld + kk] : 0.0;
-        double v = 0.0;
+            for (int kk = 0; kk < kOrthB; ++kk) bv[kk] = kk < nb ? B[(int64_t)i * ld + kk] : 0.0;
 #pragma unroll
-        for (int kk = 0; kk < kOrthB; ++kk) v = fma(bv[kk], Ri[kk * kOrthB + lq], v);
-        if (hasP) {
+            for (int kk = 0; kk < kOrthB; ++kk) v = fma(bv[kk], Ri[kk * kOrthB + lq], v);
+            if (hasP) {
 #pragma unroll
-          for (int kk = 0; kk < kOrthB; ++kk) v = fma(-P[(int64_t)i * ld + kk], Ds[kk * kOrthB + lq], v);
+              for (int kk = 0; kk < kOrthB; ++kk) v = fma(-P[(int64_t)i * ld + kk], Ds[kk * kOrthB + lq], v);
+            }
+            if (lq < nb) B[(int64_t)i * ld + lq] = v;
+          }
+          tile[lq * (kWave + 1) + ii] = v;
         }
-        if (lq < nb) {
-          B[(int64_t)i * ld + lq] = v;
-          Y[(int64_t)i * ld + j0 + lq] = (T)v;
+        __syncthreads();
+        for (int q = tid; q < kWave * kOrthB; q += kEigBlock) {
+          const int lq = q / kWave, ii = q - lq * kWave, i = i0 + ii;
+          if (i < m && lq < nb) Qz[(int64_t)(j0 + lq) * ld + i] = (T)tile[lq * (kWave + 1) + ii];
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
     if (tid == 0 && s_bad) {
       // a block without full rank: the eigensolver failed for this submatrix
@@ -1062,23 +984,78 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
 }
 
 // ------------------------------------------------------ back-transform
-// Q = Q1 Z on MFMA (Q1 in the W slab, Z^T = Y in the S slab).
+// Q = Q1 Z with Q1 = H_0 H_1 ... H_{m-3} applied to Z in place, block by
+// block from the last one: for kNBq consecutive reflectors with vectors V
+// (rows k0+1.., zeros above each vector's first entry) and compact-WY
+// factor T (H_k0 ... H_k0+nb-1 = I - V T V^T; T[c][c] = tau_c,
+// T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c]),
+//   Q[k0+1:, :] -= V (T (V^T Q[k0+1:, :])) = V ((V T^T)^T Q[k0+1:, :]).
+// Per block: G = V^T V, T (one wave), VT = V T^T, Wm = VT^T Q_sub,
+// Q_sub -= V Wm, all products on MFMA; 2 m^3 flops in all.
+constexpr int kNBq = 64;
+
+size_t apply_scratch_elems(int ld) { return 2 * (size_t)kNBq * kNBq + 2 * (size_t)kNBq * ld; }
+
 template <class T>
-__global__ __launch_bounds__(kBigBlock) void k_back_transform(LargeArgs a) {
+__global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
+  __shared__ double Ts[kNBq * kNBq];
+  const int tid = threadIdx.x;
   T* gsm = (T*)dyn;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
-    if (a.only_flagged && !(a.flags[it] & LF_FALLBACK)) continue;
+    if (skip_item(a, it)) continue;
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
-    const T* Q1 = at<T>((const void*)a.W, a.off[it]);
-    const T* Y = at<T>((const void*)a.S, a.off[it]);
+    const T* S = at<T>((const void*)a.S, a.off[it]);
     T* Q = at<T>(a.Q, a.qoff[it]);
-    wg_gemm<T, kBigNW, false, true>(m, m, m, T(1), Q1, ld, Y, ld, T(0), Q, ld, gsm);
+    const T* tau = at<T>((const void*)a.tau, a.voff[it]);
+    // scratch (type T): G, T (kNBq x kNBq each), VT (ld x kNBq), Wm (kNBq x ld)
+    T* Gm = at<T>(a.escr, a.eoff[it]);
+    T* Tm = Gm + kNBq * kNBq;
+    T* VT = Tm + kNBq * kNBq;
+    T* Wm = VT + (int64_t)kNBq * ld;
+    const int nref = m - 2;
+    for (int t = (nref + kNBq - 1) / kNBq - 1; t >= 0; --t) {
+      const int k0 = t * kNBq;
+      const int nbt = (nref - k0) < kNBq ? (nref - k0) : kNBq;
+      const int n2 = m - k0 - 1;
+      const T* V = S + (int64_t)k0 * ld + (k0 + 1);
+      T* Qs = Q + (k0 + 1);
+      wg_gemm<T, kBigNW, true, false, false, 2>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
+      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) {
+        const int c = q / kNBq, r = q - c * kNBq;
+        Ts[q] = (r < nbt && c < nbt) ? (double)Gm[q] : 0.0;  // column-major, Ts[c*kNBq + r]
+      }
+      __syncthreads();
+      // T column by column, in place over G: column c of G (rows < c) is
+      // read before column c of T replaces it
+      if (tid < kWave) {
+        for (int c = 0; c < nbt; ++c) {
+          const double tc = (double)tau[k0 + c];
+          double v = 0.0;
+          if (tid < c) {
+            for (int s2 = tid; s2 < c; ++s2) v = fma(Ts[s2 * kNBq + tid], Ts[c * kNBq + s2], v);
+            v = -tc * v;
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (tid < c) Ts[c * kNBq + tid] = v;
+          if (tid == c) Ts[c * kNBq + c] = tc;
+          if (tid > c && tid < kNBq) Ts[c * kNBq + tid] = 0.0;
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      __syncthreads();
+      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) Tm[q] = (T)Ts[q];
+      __syncthreads();
+      // VT = V T^T (n2 x nbt), Wm = VT^T Q_sub (nbt x m), Q_sub -= V Wm
+      wg_gemm<T, kBigNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0), VT, ld, gsm);
+      wg_gemm<T, kBigNW, true, false, false, 2>(nbt, m, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
+      wg_gemm<T, kBigNW, false, false, false, 2>(n2, m, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
+    }
   }
 }
 
@@ -1167,8 +1144,8 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
       }
     }
     __syncthreads();
-    wg_gemm<T, kBigNW, false, false>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
-    wg_gemm<T, kBigNW, false, true, true>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
+    wg_gemm<T, kBigNW, false, false, false, 2>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
+    wg_gemm<T, kBigNW, false, true, true, 2>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
     VT* ga = (VT*)a.ga;
     for (int k = wv; k < m; k += kBigNW) {
       const int r = R[k];
@@ -1223,15 +1200,6 @@ hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_form_q1(const LargeArgs& a, hipStream_t s) {
-  if (a.n_items <= 0) return hipSuccess;
-  if (a.fp64)
-    hipLaunchKernelGGL(k_form_q1<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
-  else
-    hipLaunchKernelGGL(k_form_q1<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
-  return hipGetLastError();
-}
-
 size_t eig_lds_bytes(int max_m) { return (size_t)max_m * (4 * sizeof(double) + 2 * sizeof(int)); }
 
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s) {
@@ -1257,9 +1225,9 @@ hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s) {
 hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.fp64)
-    hipLaunchKernelGGL(k_back_transform<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
+    hipLaunchKernelGGL(k_apply_reflectors<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
   else
-    hipLaunchKernelGGL(k_back_transform<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
+    hipLaunchKernelGGL(k_apply_reflectors<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
   return hipGetLastError();
 }
 

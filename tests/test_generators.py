@@ -50,3 +50,12 @@ def test_special_cases():
     for c in (G.diagonal_spd(20), G.block_diagonal_spd((2, 3)), G.dense_spd(10),
               G.random_sparse_spd(40, 0.1), G.arrowhead_spd(12), G.explicit_zero_pattern()):
         _check_csr(c)
+
+
+def test_dense_with_spectrum_has_that_spectrum():
+    eigs = np.concatenate([np.full(5, 1.0), np.full(3, 2.5), np.linspace(3.0, 4.0, 4)])
+    c = G.dense_with_spectrum(eigs)
+    a = c.dense()
+    assert np.array_equal(a, a.T)
+    assert np.allclose(np.linalg.eigvalsh(a), np.sort(eigs), atol=1e-13)
+    assert c.nnz == 144

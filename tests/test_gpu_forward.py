@@ -235,3 +235,59 @@ def test_sparse_csr_wrapper_reuses_pattern(gpu_lib):
     assert torch.equal(xcsr.col_indices(), a.col_indices())
     ref, _ = oracle_forward(csr, 2)
     assert rel_fro(xcsr.values().cpu().numpy(), ref) <= TOL64
+
+
+def test_repeated_eigenvalues(gpu_lib):
+    """Exactly repeated eigenvalues (multiplicities 40, 40, 30) in one dense
+    submatrix of order 150: the tridiagonal eigensolver sees split blocks
+    and near-coincident eigenvalues."""
+    eigs = np.concatenate([np.full(40, 1.0), np.full(40, 2.0), np.full(30, 3.5), np.linspace(4.0, 9.0, 40)])
+    csr = G.dense_with_spectrum(eigs)
+    banner("repeated eigenvalues, dense n=150")
+    for p in (1, 2):
+        x, st = gpu_forward(csr, p)
+        ref, _ = oracle_forward(csr, p)
+        err = rel_fro(x, ref)
+        print(f"p={p} rel_err={err:.3e} status={st}", flush=True)
+        assert err <= TOL64 and st["unconverged"] == 0
+
+
+@pytest.mark.parametrize("ctol", [0.0, 1e-2, 0.5])
+def test_cluster_tolerance_paths(ctol, gpu_lib):
+    """Twisted factorisation only (0), many clusters (1e-2), every eigenvalue
+    of a block in one cluster (0.5, inverse iteration throughout): all meet
+    the FP64 bar."""
+    from paper_1710_10899_amd import _lib
+    csr = G.overlap_matrix(n_atoms=24, nbf=13, rcut=4.14, kappa=100.0, seed=83)
+    banner(f"cluster tolerance {ctol}")
+    _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, ctol)
+    try:
+        x, st = gpu_forward(csr, 2)
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-5)
+    ref, _ = oracle_forward(csr, 2)
+    err = rel_fro(x, ref)
+    print(f"ctol={ctol} rel_err={err:.3e} status={st}", flush=True)
+    assert err <= TOL64 and st["unconverged"] == 0
+
+
+def test_results_independent_of_launch_grid(gpu_lib, tmp_path, monkeypatch):
+    """The per-submatrix arithmetic does not depend on how many workgroups
+    the persistent kernels run: bit-identical outputs for other tables."""
+    from paper_1710_10899_amd import _lib
+    from paper_1710_10899_amd import autotune
+    csr = G.overlap_matrix(n_atoms=40, nbf=13, rcut=4.14, kappa=100.0, seed=84)
+    banner("launch-grid independence")
+    ref, _ = gpu_forward(csr, 2)
+    table = autotune.DEFAULTS
+    for kind, bpc in ((1, 1), (1, 3), (2, 1)):
+        table = autotune.table_with(table, kind, 1024, bpc)
+    path = tmp_path / "tune.txt"
+    autotune.write_table(path, table)
+    monkeypatch.setenv("SUBMAT_TUNE_FILE", str(path))
+    _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+    try:
+        x, _ = gpu_forward(csr, 2)
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 0)
+    assert np.array_equal(x, ref)

@@ -175,6 +175,21 @@ def dense_spd(n: int = 48, seed: int = BASE_SEED + 13, kappa: float = 20.0) -> C
     return _from_coo(ii.ravel(), jj.ravel(), b.ravel(), n, dict(kind="dense", seed=seed))
 
 
+def dense_with_spectrum(eigs, seed: int = BASE_SEED + 17) -> CSR:
+    """Dense symmetric matrix Q diag(eigs) Q^T with Q a seeded random
+    orthogonal matrix (QR of a Gaussian matrix): prescribed, possibly
+    repeated, eigenvalues."""
+    rng = _rng(seed)
+    eigs = np.asarray(eigs, dtype=np.float64)
+    n = eigs.shape[0]
+    q, r = np.linalg.qr(rng.standard_normal((n, n)))
+    q = q * np.sign(np.diag(r))
+    b = (q * eigs) @ q.T
+    b = 0.5 * (b + b.T)
+    ii, jj = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return _from_coo(ii.ravel(), jj.ravel(), b.ravel(), n, dict(kind="dense_spectrum", seed=seed))
+
+
 def random_sparse_spd(n: int = 200, density: float = 0.05, seed: int = BASE_SEED + 14,
                       kappa: float = 10.0) -> CSR:
     """Random symmetric pattern (each i<j kept with probability density),

@@ -985,22 +985,62 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
 
 // ------------------------------------------------------ back-transform
 // Q = Q1 Z with Q1 = H_0 H_1 ... H_{m-3} applied to Z in place, block by
-// block from the last one: for kNBq consecutive reflectors with vectors V
-// (rows k0+1.., zeros above each vector's first entry) and compact-WY
-// factor T (H_k0 ... H_k0+nb-1 = I - V T V^T; T[c][c] = tau_c,
-// T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c]),
+// block from the last one. A block of up to kNBq consecutive reflectors
+// with vectors V (rows k0+1.., zeros above each vector's first entry) acts
+// as H_k0 ... H_k0+nb-1 = I - V T V^T, so
 //   Q[k0+1:, :] -= V (T (V^T Q[k0+1:, :])) = V ((V T^T)^T Q[k0+1:, :]).
-// Per block: G = V^T V, T (one wave), VT = V T^T, Wm = VT^T Q_sub,
-// Q_sub -= V Wm, all products on MFMA; 2 m^3 flops in all.
-constexpr int kNBq = 64;
+// T is upper triangular: for a half of kNBh reflectors, T[c][c] = tau_c
+// and T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c] (one wave, in LDS);
+// the two halves merge as [[T1, -T1 (V1^T V2) T2], [0, T2]]. All products
+// on MFMA; 2 m^3 flops in all, and one read and write of Q per block.
+constexpr int kNBq = 128;
+constexpr int kNBh = kNBq / 2;
 
-size_t apply_scratch_elems(int ld) { return 2 * (size_t)kNBq * kNBq + 2 * (size_t)kNBq * ld; }
+size_t apply_scratch_elems(int ld) {
+  return 2 * (size_t)kNBq * kNBq + (size_t)kNBh * kNBh + 2 * (size_t)kNBq * ld;
+}
+
+// Upper-triangular compact-WY factor of reflectors c0 .. c0+nh-1 of a block
+// from its Gram matrix G (column-major, leading dimension kNBq), into
+// columns/rows c0.. of Tm (same layout); called by the whole workgroup.
+template <class T>
+__device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh, double* Ts) {
+  const int tid = threadIdx.x;
+  for (int q = tid; q < kNBh * kNBh; q += kBigBlock) {
+    const int c = q / kNBh, r = q - c * kNBh;
+    Ts[q] = (r < nh && c < nh) ? (double)Gm[(int64_t)(c0 + c) * kNBq + (c0 + r)] : 0.0;  // Ts[c*kNBh + r]
+  }
+  __syncthreads();
+  // column by column, in place over G: column c of G (rows < c) is read
+  // before column c of T replaces it
+  if (tid < kWave) {
+    for (int c = 0; c < nh; ++c) {
+      const double tc = (double)tau[c0 + c];
+      double v = 0.0;
+      if (tid < c) {
+        for (int s2 = tid; s2 < c; ++s2) v = fma(Ts[s2 * kNBh + tid], Ts[c * kNBh + s2], v);
+        v = -tc * v;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (tid < c) Ts[c * kNBh + tid] = v;
+      if (tid == c) Ts[c * kNBh + c] = tc;
+      if (tid > c && tid < kNBh) Ts[c * kNBh + tid] = 0.0;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < kNBh * kNBh; q += kBigBlock) {
+    const int c = q / kNBh, r = q - c * kNBh;
+    if (r < nh && c < nh) Tm[(int64_t)(c0 + c) * kNBq + (c0 + r)] = (T)Ts[q];
+  }
+  __syncthreads();
+}
 
 template <class T>
 __global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
-  __shared__ double Ts[kNBq * kNBq];
+  __shared__ double Ts[kNBh * kNBh];
   const int tid = threadIdx.x;
   T* gsm = (T*)dyn;
   for (;;) {
@@ -1013,44 +1053,34 @@ __global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
     const T* S = at<T>((const void*)a.S, a.off[it]);
     T* Q = at<T>(a.Q, a.qoff[it]);
     const T* tau = at<T>((const void*)a.tau, a.voff[it]);
-    // scratch (type T): G, T (kNBq x kNBq each), VT (ld x kNBq), Wm (kNBq x ld)
+    // scratch (type T): G, T (kNBq x kNBq each), X (kNBh x kNBh),
+    // VT (ld x kNBq), Wm (kNBq x ld)
     T* Gm = at<T>(a.escr, a.eoff[it]);
     T* Tm = Gm + kNBq * kNBq;
-    T* VT = Tm + kNBq * kNBq;
+    T* Xm = Tm + kNBq * kNBq;
+    T* VT = Xm + kNBh * kNBh;
     T* Wm = VT + (int64_t)kNBq * ld;
     const int nref = m - 2;
     for (int t = (nref + kNBq - 1) / kNBq - 1; t >= 0; --t) {
       const int k0 = t * kNBq;
       const int nbt = (nref - k0) < kNBq ? (nref - k0) : kNBq;
       const int n2 = m - k0 - 1;
+      const int nh1 = nbt < kNBh ? nbt : kNBh, nh2 = nbt - nh1;
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
       T* Qs = Q + (k0 + 1);
-      wg_gemm<T, kBigNW, true, false, false, 2>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
-      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) {
-        const int c = q / kNBq, r = q - c * kNBq;
-        Ts[q] = (r < nbt && c < nbt) ? (double)Gm[q] : 0.0;  // column-major, Ts[c*kNBq + r]
+      wg_gemm<T, kBigNW, true, false, false, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
+      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) Tm[q] = T(0);
+      __syncthreads();
+      wy_factor_half<T>(Gm, Tm, tau + k0, 0, nh1, Ts);
+      if (nh2 > 0) {
+        wy_factor_half<T>(Gm, Tm, tau + k0, kNBh, nh2, Ts);
+        // T12 = -T1 (G12 T2): X = G12 T2, then T12 = -T1 X
+        const T* G12 = Gm + (int64_t)kNBh * kNBq;                  // rows 0.., columns kNBh..
+        const T* T22 = Tm + (int64_t)kNBh * kNBq + kNBh;
+        wg_gemm<T, kBigNW, false, false, false, 1>(nh1, nh2, nh2, T(1), G12, kNBq, T22, kNBq, T(0), Xm, kNBh, gsm);
+        wg_gemm<T, kBigNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
+                                                   Tm + (int64_t)kNBh * kNBq, kNBq, gsm);
       }
-      __syncthreads();
-      // T column by column, in place over G: column c of G (rows < c) is
-      // read before column c of T replaces it
-      if (tid < kWave) {
-        for (int c = 0; c < nbt; ++c) {
-          const double tc = (double)tau[k0 + c];
-          double v = 0.0;
-          if (tid < c) {
-            for (int s2 = tid; s2 < c; ++s2) v = fma(Ts[s2 * kNBq + tid], Ts[c * kNBq + s2], v);
-            v = -tc * v;
-          }
-          __builtin_amdgcn_wave_barrier();
-          if (tid < c) Ts[c * kNBq + tid] = v;
-          if (tid == c) Ts[c * kNBq + c] = tc;
-          if (tid > c && tid < kNBq) Ts[c * kNBq + tid] = 0.0;
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      __syncthreads();
-      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) Tm[q] = (T)Ts[q];
-      __syncthreads();
       // VT = V T^T (n2 x nbt), Wm = VT^T Q_sub (nbt x m), Q_sub -= V Wm
       wg_gemm<T, kBigNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0), VT, ld, gsm);
       wg_gemm<T, kBigNW, true, false, false, 2>(nbt, m, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);

@@ -24,6 +24,17 @@ FP64_VALU_PEAK = 78.6       # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP32_VALU_PEAK = 78.6       # unpacked FP32 VALU: same lane rate as FP64
 HBM_PEAK_GBS = 8000.0
 
+WORKLOAD_NAMES = {
+    1: "banded SPD matrix, n=1024, half-bandwidth 8, p={p}; forward + adjoint",
+    2: "overlap-type SPD matrix, 512 atoms x 13 basis functions (n=6656), ~400 stored entries per column, "
+       "kappa={kappa:g}, p={p}; forward + adjoint",
+    3: "mixed-density overlap-type SPD matrix, 4096 atoms x 13 (n=53248), orders 52-1534, kappa={kappa:g}, "
+       "p={p}; forward + adjoint",
+    4: "overlap-type SPD matrix, 1024 atoms x 13 (n=13312), kappa={kappa:g}, p={p}; forward + adjoint",
+    5: "overlap-type SPD matrix, 16384 atoms x 13 (n=212992), ~500 stored entries per column, kappa={kappa:g}, "
+       "p={p}; forward + adjoint",
+}
+
 # library kernel (substring of its symbol) -> phase of submat_time_phases
 KERNEL_PHASE = {"k_small": "small-jacobi", "k_gather_large": "gather", "k_tridiagonalise": "tridiagonalise",
                 "k_tridiag_eig": "tridiagonal-eig", "k_eig_orth": "reorthogonalise",
@@ -172,13 +183,18 @@ def _pool_work(cols):
     return len(cols)
 
 
-def cpu_baseline(csr, w, p, n_sample=384):
+def cpu_baseline(csr, w, p, n_sample=None):
     """The FP64 oracle (forward + adjoint per column) on a seeded sample of
     columns, one single-threaded-BLAS worker process per host core."""
     import multiprocessing as mp
 
     import numpy as np
     cores = min(os.cpu_count() or 1, 16)
+    if n_sample is None:
+        # about 20 s of CPU work: 384 columns at the 6656-column workload's
+        # mean m^3, scaled by this workload's
+        m3 = float((csr.row_sizes().astype(np.float64) ** 3).mean())
+        n_sample = int(max(32, min(csr.n, 384 * 6.9e7 / m3)))
     rng = np.random.default_rng(171010899 + 400)
     cols = np.sort(rng.choice(csr.n, min(n_sample, csr.n), replace=False))
     chunks = [cols[i::cores * 4].tolist() for i in range(cores * 4)]
@@ -214,6 +230,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32_mixed"])
     ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="named synthetic workload (2 = the 6656-column overlap matrix the metric is quoted on)")
+    ap.add_argument("--kappa", type=float, default=None, help="condition number of the workload (its default if unset)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true")
@@ -241,8 +260,8 @@ def main():
     _lib.load()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    csr = G.make_config(2)
-    w = G.upstream_gradient(csr, G.BASE_SEED + 2 + 100)
+    csr = G.make_config(args.workload, kappa=args.kappa)
+    w = G.upstream_gradient(csr, G.BASE_SEED + args.workload + 100)
     log(f"workload n={csr.n} nnz={csr.nnz} m={csr.row_sizes().min()}..{csr.row_sizes().max()} "
         f"generated in {time.perf_counter() - t0:.1f}s")
     m = csr.row_sizes()
@@ -254,8 +273,13 @@ def main():
     x = torch.empty_like(va)
     ga = torch.empty_like(va)
     nb = sm.saved_bytes(rp, ci, dt, args.precision)
-    saved = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
-    log(f"saved eigenvector buffer {nb / 2**30:.2f} GiB")
+    free_b, _ = torch.cuda.mem_get_info()
+    if nb <= 0.4 * free_b:
+        saved = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
+        log(f"saved eigenvector buffer {nb / 2**30:.2f} GiB")
+    else:
+        saved = None
+        log(f"saved eigenvectors would need {nb / 2**30:.1f} GiB: the adjoint recomputes them")
     prec = args.precision
 
     def step():
@@ -301,9 +325,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == "f64" else "f32+f64-fallback",
         "data": "synthetic",
-        "config": {"workload": "overlap-type SPD matrix, 512 atoms x 13 basis functions (n=6656), "
-                               "~400 stored entries per column, kappa=1e2, p=2; forward + adjoint",
+        "config": {"workload": WORKLOAD_NAMES[args.workload].format(kappa=csr.meta.get("kappa_target", 0.0),
+                                                                    p=args.p),
                    "n": csr.n, "nnz": csr.nnz, "p": args.p, "precision": prec,
+                   "eigenvectors": "kept between forward and adjoint" if saved is not None else "recomputed",
                    "m_min": int(m.min()), "m_mean": float(m.mean()), "m_max": int(m.max()),
                    "parallelism": "single GPU"},
         "gflops_algorithmic": gflops,

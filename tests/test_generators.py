@@ -59,3 +59,14 @@ def test_dense_with_spectrum_has_that_spectrum():
     assert np.array_equal(a, a.T)
     assert np.allclose(np.linalg.eigvalsh(a), np.sort(eigs), atol=1e-13)
     assert c.nnz == 144
+
+
+def test_cached_extremes_match_lanczos_on_a_smaller_matrix():
+    """The cached-extremes path of shift_to_kappa places the same shift as
+    computing the extremes (checked where Lanczos is cheap)."""
+    csr = G.overlap_matrix(n_atoms=300, nbf=13, rcut=4.14, kappa=None, seed=5)
+    ext = G.extreme_eigenvalues(csr)
+    a = G.shift_to_kappa(csr, 1e4)
+    b = G.shift_to_kappa(csr, 1e4, ext)
+    assert abs(a.meta["sigma"] - b.meta["sigma"]) <= 1e-9 * abs(b.meta["sigma"])
+    assert abs(b.meta["lmax"] / b.meta["lmin"] - 1e4) <= 1e-6 * 1e4

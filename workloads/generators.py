@@ -81,9 +81,10 @@ def extreme_eigenvalues(csr: CSR) -> tuple[float, float]:
     return float(lmin), float(lmax)
 
 
-def shift_to_kappa(csr: CSR, kappa: float) -> CSR:
-    """Add sigma*I so that lambda_max/lambda_min of the result equals kappa."""
-    lmin, lmax = extreme_eigenvalues(csr)
+def shift_to_kappa(csr: CSR, kappa: float, extremes: tuple[float, float] | None = None) -> CSR:
+    """Add sigma*I so that lambda_max/lambda_min of the result equals kappa.
+    `extremes` = (lambda_min, lambda_max) of csr when already known."""
+    lmin, lmax = extremes if extremes is not None else extreme_eigenvalues(csr)
     sigma = (lmax - kappa * lmin) / (kappa - 1.0)
     diag_pos = _diag_positions(csr)
     vals = csr.vals.copy()
@@ -353,16 +354,29 @@ CONFIGS = {
 }
 
 
-def make_config(idx: int, kappa: float | None = None) -> CSR:
+# Extreme eigenvalues (lambda_min, lambda_max) of the unshifted matrices of
+# the two largest workloads, as printed by `python -m workloads.compute_extremes`
+# (Lanczos, tolerance 1e-13): the shift is then placed without repeating it.
+UNSHIFTED_EXTREMES = {
+    3: (-2.3929758500221108, 86.66767021272706),
+    5: (-2.1097858092000483, 62.6631285096728),
+}
+
+
+def make_config(idx: int, kappa: float | None = None, unshifted: bool = False) -> CSR:
     seed = BASE_SEED + idx
     if idx == 1:
         return banded_spd(1024, 8, seed=seed)
     if idx == 2:
-        return overlap_matrix(512, 0.1, 13, 4.14, kappa or 1e2, seed=seed)
-    if idx == 3:
-        return mixed_density_overlap(4096, kappa=kappa or 1e2, seed=seed)
+        return overlap_matrix(512, 0.1, 13, 4.14, None if unshifted else (kappa or 1e2), seed=seed)
     if idx == 4:
-        return overlap_matrix(1024, 0.1, 13, 4.14, kappa or 1e2, seed=seed)
-    if idx == 5:
-        return overlap_matrix(16384, 0.1, 13, 4.47, kappa or 1e6, seed=seed)
-    raise ValueError(f"unknown workload {idx}")
+        return overlap_matrix(1024, 0.1, 13, 4.14, None if unshifted else (kappa or 1e2), seed=seed)
+    if idx == 3:
+        csr = mixed_density_overlap(4096, kappa=None, seed=seed)
+        k = kappa or 1e2
+    elif idx == 5:
+        csr = overlap_matrix(16384, 0.1, 13, 4.47, None, seed=seed)
+        k = kappa or 1e6
+    else:
+        raise ValueError(f"unknown workload {idx}")
+    return csr if unshifted else shift_to_kappa(csr, k, UNSHIFTED_EXTREMES.get(idx))

@@ -666,6 +666,7 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
   __shared__ int s_item;
   __shared__ double red[4 * kEigNW];
   __shared__ int ired[2 * kEigNW];
+  __shared__ int msc[kEigBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int M = a.max_m;
   double* d = dyn;
@@ -746,9 +747,28 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
     ghi += pad;
     // eigenvalues: one lane each, to a few ulps or 1e-3 eps ||T||
     const double atol = 1e-3 * kUnitRoundoff * tn + pivmin;
+    // multisection start for an unsplit T: counts at kEigBlock evenly
+    // spaced points (one Sturm pass per thread) narrow every bracket by a
+    // factor kEigBlock + 1 before the bisection
+    const bool one_block = be[0] == m;
+    const double hstep = (ghi - glo) / (kEigBlock + 1);
+    if (one_block) msc[tid] = sturm_count(d, e2, 0, m, glo + (tid + 1) * hstep, pivmin);
+    __syncthreads();
     for (int jj = tid; jj < m; jj += kEigBlock) {
       const int s = bs[jj], t = be[jj], k = jj - s;
       double lo = glo, hi = ghi;
+      if (one_block) {
+        // the last point with count <= k, and the next one
+        int a2 = 0, b2 = kEigBlock;  // counts at points a2-1 (glo for 0) ... search over msc
+        while (a2 < b2) {
+          const int mid = (a2 + b2) >> 1;
+          if (msc[mid] <= k) a2 = mid + 1;
+          else b2 = mid;
+        }
+        // points 0..a2-1 have count <= k, point a2 (if any) has count > k
+        lo = a2 > 0 ? glo + a2 * hstep : glo;
+        hi = a2 < kEigBlock ? glo + (a2 + 1) * hstep : ghi;
+      }
       for (int iter = 0; iter < 256; ++iter) {
         const double mid = 0.5 * (lo + hi);
         if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;

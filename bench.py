@@ -4,6 +4,10 @@ n = 6656, ~400 stored entries per column, kappa = 1e2, p = 2), inputs resident
 in HBM. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|f32_mixed]
+                  [--workload 1..5] [--fn inv_root|root|power] [--p P] [--alpha A]
+
+The default is the inverse square root; --fn selects the other spectral
+functions (positive p-th root, real power), which run the same kernels.
 """
 from __future__ import annotations
 
@@ -171,19 +175,19 @@ def summarise_profile(d: str, command: str) -> None:
 _W = {}
 
 
-def _pool_init(rowptr, colind, vals, wvals, p):
-    _W.update(rowptr=rowptr, colind=colind, vals=vals, wvals=wvals, p=p)
+def _pool_init(rowptr, colind, vals, wvals, p, fn):
+    _W.update(rowptr=rowptr, colind=colind, vals=vals, wvals=wvals, p=p, fn=fn)
 
 
 def _pool_work(cols):
     import oracle
-    segs, _ = oracle.forward_columns(_W["rowptr"], _W["colind"], _W["vals"], _W["p"], cols)
+    segs, _ = oracle.forward_columns(_W["rowptr"], _W["colind"], _W["vals"], _W["p"], cols, _W["fn"])
     oracle.adjoint(_W["rowptr"], _W["colind"], _W["vals"], len(_W["rowptr"]) - 1, _W["p"], _W["wvals"],
-                   cols=cols, check=False)
+                   cols=cols, check=False, fn=_W["fn"])
     return len(cols)
 
 
-def cpu_baseline(csr, w, p, n_sample=None):
+def cpu_baseline(csr, w, p, n_sample=None, fn="inv_root"):
     """The FP64 oracle (forward + adjoint per column) on a seeded sample of
     columns, one single-threaded-BLAS worker process per host core."""
     import multiprocessing as mp
@@ -204,7 +208,7 @@ def cpu_baseline(csr, w, p, n_sample=None):
         os.environ[k] = "1"
     try:
         ctx = mp.get_context("spawn")
-        with ctx.Pool(cores, initializer=_pool_init, initargs=(csr.rowptr, csr.colind, csr.vals, w, p)) as pool:
+        with ctx.Pool(cores, initializer=_pool_init, initargs=(csr.rowptr, csr.colind, csr.vals, w, p, fn)) as pool:
             pool.map(_pool_work, [[int(cols[0])]] * cores)  # workers up and warm
             t0 = time.perf_counter()
             done = sum(pool.map(_pool_work, chunks))
@@ -229,7 +233,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32_mixed"])
-    ap.add_argument("--p", type=int, default=2)
+    ap.add_argument("--p", type=int, default=2, help="root order of the inverse root / root functions")
+    ap.add_argument("--fn", default="inv_root", choices=["inv_root", "root", "power"],
+                    help="spectral function: lambda^(-1/p), lambda^(1/p) or lambda^alpha")
+    ap.add_argument("--alpha", type=float, default=0.7, help="exponent of --fn power")
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="named synthetic workload (2 = the 6656-column overlap matrix the metric is quoted on)")
     ap.add_argument("--kappa", type=float, default=None, help="condition number of the workload (its default if unset)")
@@ -281,10 +288,14 @@ def main():
         saved = None
         log(f"saved eigenvectors would need {nb / 2**30:.1f} GiB: the adjoint recomputes them")
     prec = args.precision
+    fn = args.fn
+    param = args.alpha if fn == "power" else args.p
+    fn_name = {"inv_root": f"p={args.p}", "root": f"f=lambda^(1/{args.p})",
+               "power": f"f=lambda^{args.alpha:g}"}[fn]
 
     def step():
-        sm.invroot_fwd(rp, ci, va, args.p, prec, saved, out=x)
-        sm.invroot_bwd(rp, ci, va, gx, args.p, prec, saved, out=ga)
+        sm.matfun_fwd(rp, ci, va, fn, param, prec, saved, out=x)
+        sm.matfun_bwd(rp, ci, va, gx, fn, param, prec, saved, out=ga)
 
     if args.copy_probe:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -326,8 +337,8 @@ def main():
         "dtype": "f64" if prec == "f64" else "f32+f64-fallback",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_NAMES[args.workload].format(kappa=csr.meta.get("kappa_target", 0.0),
-                                                                    p=args.p),
-                   "n": csr.n, "nnz": csr.nnz, "p": args.p, "precision": prec,
+                                                                    p=args.p).replace(f"p={args.p}", fn_name),
+                   "n": csr.n, "nnz": csr.nnz, "function": fn, "param": param, "precision": prec,
                    "eigenvectors": "kept between forward and adjoint" if saved is not None else "recomputed",
                    "m_min": int(m.min()), "m_mean": float(m.mean()), "m_max": int(m.max()),
                    "parallelism": "single GPU"},
@@ -337,7 +348,7 @@ def main():
     }
 
     if not args.no_phases:
-        ph = sm.time_phases(rp, ci, va, args.p, prec, grad_x=gx)
+        ph = sm.time_phases(rp, ci, va, param, prec, grad_x=gx, fn=fn)
         counters = _lib.submat_query_counters(torch.cuda.current_stream().cuda_stream, 4)
         table = {}
         for k, (ms, nl) in ph.items():
@@ -375,11 +386,11 @@ def main():
         sci = torch.from_numpy(small.colind).cuda()
         sva = torch.from_numpy(small.vals).cuda()
         sgx = torch.from_numpy(G.upstream_gradient(small, 5)).cuda()
-        sm.invroot_fwd(srp, sci, sva, args.p, "f64_plain")
+        sm.matfun_fwd(srp, sci, sva, fn, param, "f64_plain")
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        sm.invroot_fwd(srp, sci, sva, args.p, "f64_plain")
-        sm.invroot_bwd(srp, sci, sva, sgx, args.p, "f64_plain")
+        sm.matfun_fwd(srp, sci, sva, fn, param, "f64_plain")
+        sm.matfun_bwd(srp, sci, sva, sgx, fn, param, "f64_plain")
         torch.cuda.synchronize()
         plain_rate = small.n / (time.perf_counter() - tp)
         ms_ = small.row_sizes().astype(float)
@@ -390,7 +401,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(csr, w, args.p)
+        out["cpu_baseline"] = cpu_baseline(csr, w, param, fn=fn)
         log(f"cpu baseline {out['cpu_baseline']['value']:.1f} submatrices/s")
 
     print(json.dumps(out), flush=True)

@@ -1,9 +1,13 @@
 /*
  * submat.h -- C ABI of the MI355X (gfx950) submatrix-method library.
  *
- * The library computes the submatrix-method approximation X ~ A^(-1/p) of a
+ * The library computes the submatrix-method approximation X ~ f(A) of a
  * sparse symmetric positive-definite matrix A, with X restricted to A's
- * sparsity pattern (Lass et al., arXiv:1710.10899):
+ * sparsity pattern (Lass et al., arXiv:1710.10899). The paper's main case is
+ * the inverse p-th root f(lambda) = lambda^(-1/p); its subsection
+ * "Applicability to other matrix operations" (Section 4) extends the method
+ * to positive p-th roots, and the same per-submatrix spectral route serves
+ * any real power lambda^alpha:
  *
  *   Section 3.1 (Algorithm "Construction of submatrices"): for column j,
  *     R_j = rows holding a stored entry of column j, S_j = A[R_j, R_j].
@@ -38,7 +42,7 @@
  * Errors: every int-returning call returns SUBMAT_OK (0) or a negative code;
  * submat_strerror() names it. Invalid input is reported synchronously and
  * nothing is written. Numerical failures are asynchronous: a submatrix with
- * an eigenvalue <= 0 (no real inverse p-th root) or whose eigensolver did not
+ * an eigenvalue <= 0 (outside the domain of the functions above) or whose eigensolver did not
  * converge yields NaN in its output segment and is counted in device
  * counters that submat_query_status() reads. The library never aborts and
  * never prints.
@@ -96,21 +100,29 @@ extern "C" {
                                     built-in table; get returns 1 when a file is in use.
                                     The table is first read at the first call. */
 
+/* spectral function f applied to every submatrix, and the meaning of `param` */
+#define SUBMAT_FN_INV_ROOT 0  /* f(lambda) = lambda^(-1/p), param = p, integer >= 1 (Sections 3-4) */
+#define SUBMAT_FN_ROOT     1  /* f(lambda) = lambda^(1/p),  param = p, integer >= 1 (Section 4,
+                                 "Applicability to other matrix operations") */
+#define SUBMAT_FN_POWER    2  /* f(lambda) = lambda^alpha,  param = alpha, finite real (the same
+                                 spectral route for any real power) */
+
 /*
  * Forward: x_vals[rowptr[j] + i] = (f(S_j))[i][c_j] for every column j and
- * i < m_j, where c_j = R_j.indexof(j), f(lambda) = lambda^(-1/p)
- * (Sections 3.1-3.4).
+ * i < m_j, where c_j = R_j.indexof(j) (Sections 3.1-3.4).
  *   rowptr  int32[n+1], colind int32[nnz]: CSR pattern (see above).
  *   vals    nnz values of A, type `dtype`.
- *   p       integer >= 1.
+ *   fn      SUBMAT_FN_*; param its parameter (an invalid pair is SUBMAT_EINVAL).
  *   x_vals  nnz values of X (same type), fully written.
  *   saved   NULL, or a device buffer of submat_saved_bytes() bytes; when given, the
  *           eigenvectors and eigenvalues of every submatrix on the large-order path
- *           are kept there so that submat_invroot_bwd() need not recompute them.
+ *           are kept there so that the adjoint need not recompute them. They do
+ *           not depend on fn, so one saved buffer serves every function.
+ * f(lambda) is evaluated in FP64 from the eigenvalues in every precision mode.
  */
-int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
-                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
-                       void* x_vals, void* saved, void* stream);
+int submat_matfun_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                      int32_t n, int64_t nnz, int32_t fn, double param, int32_t dtype,
+                      int32_t precision, void* x_vals, void* saved, void* stream);
 
 /*
  * Adjoint (Daleckii-Krein; the paper has no gradient): for the loss
@@ -120,9 +132,21 @@ int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void*
  * (lambda_k - lambda_l) (f'(lambda_k) when equal) and M = G o (a b^T):
  * D_j = Q (M + M^T)/2 Q^T, and every stored pair (R_j[k], R_j[l]) at
  * position q receives D_j[k][l]. grad_a is fully written (zeroed first).
- *   saved   NULL (recompute), or the buffer filled by the submat_invroot_fwd() call
- *           with the same pattern, vals, p, dtype and precision.
+ * G is evaluated without cancellation: through alpha = lambda^(1/p) for the
+ * roots, through expm1/log1p of the eigenvalue ratio for a real power.
+ *   saved   NULL (recompute), or the buffer filled by a forward call with the
+ *           same pattern, vals, dtype and precision.
  */
+int submat_matfun_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                      int32_t n, int64_t nnz, int32_t fn, double param, int32_t dtype,
+                      int32_t precision, const void* grad_x, void* grad_a, const void* saved,
+                      void* stream);
+
+/* The inverse p-th root (the paper's main case): submat_matfun_fwd / _bwd with
+   fn = SUBMAT_FN_INV_ROOT and param = p (integer p >= 1). */
+int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
+                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
+                       void* x_vals, void* saved, void* stream);
 int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
                        int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
                        const void* grad_x, void* grad_a, const void* saved, void* stream);
@@ -174,9 +198,9 @@ int32_t submat_version(void);
  */
 #define SUBMAT_NUM_PHASES 10
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals,
-                       int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
-                       void* x_vals, const void* grad_x, void* grad_a, void* stream,
-                       double* phase_ms, int32_t* phase_launches);
+                       int32_t n, int64_t nnz, int32_t fn, double param, int32_t dtype,
+                       int32_t precision, void* x_vals, const void* grad_x, void* grad_a,
+                       void* stream, double* phase_ms, int32_t* phase_launches);
 
 #ifdef __cplusplus
 }

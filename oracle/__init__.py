@@ -12,6 +12,10 @@ from .submat_oracle import (  # noqa: F401
     inv_root,
     root,
     eig,
+    FUNCTIONS,
+    check_function,
+    spectral_function,
+    column_of_function,
     column_of_inverse_root,
     forward,
     forward_columns,

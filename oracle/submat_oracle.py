@@ -11,11 +11,16 @@ Approximate Calculation of Inverse p-th Roots of Large Sparse Matrices"):
 * Section 3.1, Algorithm "Construction of submatrices": for column j, R_j is
   the set of rows i holding an entry A[i][j]; the dense submatrix is
   S_j[k][l] = A[R_j[k]][R_j[l]].
-* Section 3.2: the operation of interest (here the inverse p-th root) is
+* Section 3.2: the operation of interest (the inverse p-th root) is
   applied to every S_j; the paper leaves the method free. This oracle takes
   the spectral route named in Section 2 for symmetric matrices: a symmetric
   eigendecomposition S = Q diag(lambda) Q^T (LAPACK through numpy) and
   f(lambda) = lambda^(-1/p).
+* Section 4, "Applicability to other matrix operations": the same method
+  applies to positive p-th roots, f(lambda) = lambda^(1/p); the spectral
+  route takes any real power f(lambda) = lambda^alpha the same way
+  (functions "inv_root", "root", "power"; the parameter is p for the roots
+  and alpha for the power).
 * Section 3.3, Algorithm "Assembly of result matrix": column j of X on rows
   R_j is the column of f(S_j) that belongs to j, i.e. column R_j.indexof(j).
 * Section 3.4: X has exactly A's pattern; in CSR/CSC its value array is the
@@ -32,9 +37,10 @@ Readings taken where the paper is silent (each is repeated in the design doc):
    result read row-wise (Section 3, row/column equivalence).
 4. S_j is symmetrised as (S_j + S_j^T)/2; this is exact for exactly
    symmetric storage.
-5. A submatrix with an eigenvalue <= 0 has no real inverse p-th root: its
-   segment is NaN and it is counted.
-6. p is an integer >= 1.
+5. A submatrix with an eigenvalue <= 0 is outside the domain of the
+   functions (no real inverse p-th root; for the others, kept to the same
+   SPD domain): its segment is NaN and it is counted.
+6. p is an integer >= 1; alpha is any finite real.
 7. The adjoint (not in the paper) is the Daleckii-Krein formula with the
    divided differences of f in closed form; gradients are per stored entry.
 """
@@ -131,47 +137,75 @@ def root(lam: np.ndarray, p: int) -> np.ndarray:
     return np.power(lam, 1.0 / p)
 
 
+FUNCTIONS = ("inv_root", "root", "power")
+
+
+def check_function(fn: str, param) -> None:
+    if fn not in FUNCTIONS:
+        raise PatternError("EINVAL", f"function must be one of {FUNCTIONS}")
+    if fn in ("inv_root", "root"):
+        if not (param >= 1 and float(param) == int(param)):
+            raise PatternError("EINVAL", "p must be an integer >= 1")
+    elif not np.isfinite(param):
+        raise PatternError("EINVAL", "alpha must be finite")
+
+
+def spectral_function(lam: np.ndarray, fn: str, param) -> np.ndarray:
+    """f(lambda) for the selected function."""
+    if fn == "inv_root":
+        return inv_root(lam, int(param))
+    if fn == "root":
+        return root(lam, int(param))
+    return np.power(lam, float(param))
+
+
 def eig(S: np.ndarray):
     lam, Q = np.linalg.eigh(S)
     return lam, Q
 
 
-def column_of_inverse_root(S: np.ndarray, c: int, p: int):
-    """Column c of S^(-1/p) = Q (f(lambda) * Q[c, :]); (x, ok)."""
+def column_of_function(S: np.ndarray, c: int, fn: str, param):
+    """Column c of f(S) = Q (f(lambda) * Q[c, :]); (x, ok)."""
     lam, Q = eig(S)
     if lam.min() <= 0.0:
         return np.full(S.shape[0], np.nan), False
-    return Q @ (inv_root(lam, p) * Q[c, :]), True
+    return Q @ (spectral_function(lam, fn, param) * Q[c, :]), True
+
+
+def column_of_inverse_root(S: np.ndarray, c: int, p: int):
+    """Column c of S^(-1/p); (x, ok)."""
+    return column_of_function(S, c, "inv_root", p)
 
 
 # ---------------------------------------------------------------------------
 # Sections 3.3/3.4: assembly into A's pattern
 
 
-def forward_columns(rowptr, colind, vals, p: int, cols):
-    """Segments of X for the given columns: {j: x_j}; and the count of
-    submatrices that were not positive definite."""
+def forward_columns(rowptr, colind, vals, p, cols, fn: str = "inv_root"):
+    """Segments of X = f(A) for the given columns: {j: x_j}; and the count
+    of submatrices that were not positive definite. `p` is the function's
+    parameter (p for the roots, alpha for the power)."""
+    check_function(fn, p)
     out = {}
     bad = 0
     for j in cols:
         R = submatrix_rows(rowptr, colind, int(j))
         c = int(np.nonzero(R == j)[0][0])
         S, _ = gather_submatrix(rowptr, colind, vals, R)
-        x, ok = column_of_inverse_root(symmetrise(S), c, p)
+        x, ok = column_of_function(symmetrise(S), c, fn, p)
         bad += 0 if ok else 1
         out[int(j)] = x
     return out, bad
 
 
-def forward(rowptr, colind, vals, n: int, p: int, check: bool = True):
+def forward(rowptr, colind, vals, n: int, p, check: bool = True, fn: str = "inv_root"):
     """X.vals on A's pattern (X.rowptr, X.colind are A's), and the number of
     non-positive-definite submatrices."""
-    if p < 1:
-        raise PatternError("EINVAL", "p must be >= 1")
+    check_function(fn, p)
     if check:
         validate(rowptr, colind, n)
     x = np.empty(len(colind), dtype=np.float64)
-    segs, bad = forward_columns(rowptr, colind, vals, p, range(n))
+    segs, bad = forward_columns(rowptr, colind, vals, p, range(n), fn)
     for j, xj in segs.items():
         x[rowptr[j]:rowptr[j + 1]] = xj
     return x, bad
@@ -181,34 +215,62 @@ def forward(rowptr, colind, vals, n: int, p: int, check: bool = True):
 # Adjoint (Daleckii-Krein); the paper has no gradient
 
 
-def divided_differences(lam: np.ndarray, p: int) -> np.ndarray:
-    """G[k,l] = (f(l_k) - f(l_l)) / (l_k - l_l), f'(l_k) on k == l, for
-    f = x^(-1/p). With a = lambda^(1/p):
-    G[k,l] = -1 / (a_k a_l sum_{i=0}^{p-1} a_k^i a_l^(p-1-i)),
-    which has no cancellation and holds for equal eigenvalues too."""
+def divided_differences(lam: np.ndarray, p, fn: str = "inv_root") -> np.ndarray:
+    """G[k,l] = (f(l_k) - f(l_l)) / (l_k - l_l), f'(l_k) where l_k == l_l.
+
+    Written so that no digits cancel:
+    * inv_root, f = x^(-1/p): with a = lambda^(1/p),
+      f(l_k) - f(l_l) = (a_l - a_k) / (a_k a_l) and
+      l_k - l_l = a_k^p - a_l^p = (a_k - a_l) s, s = sum_{i<p} a_k^i a_l^(p-1-i),
+      so G = -1 / (a_k a_l s) (also the derivative when a_k == a_l);
+    * root, f = x^(1/p): G = (a_k - a_l) / (a_k^p - a_l^p) = 1 / s;
+    * power, f = x^alpha: with t = log(l_k / l_l), l_k^alpha =
+      l_l^alpha exp(alpha t), so f(l_k) - f(l_l) = l_l^alpha expm1(alpha t),
+      and on the diagonal G = alpha l^(alpha - 1). t is formed as log1p(d),
+      d = (l_k - l_l) / l_l, when |d| < 1/2 (the difference is exact there,
+      and log1p keeps a small t to full relative accuracy), else as the log
+      of the ratio (a rounding of the ratio then moves t by about one ulp of
+      1, small against |t| > 0.4, where log1p of a d near -1 would not be)."""
+    if fn == "power":
+        alpha = float(p)
+        lk = lam[:, None] + np.zeros((1, lam.shape[0]))
+        ll = lam[None, :] + np.zeros((lam.shape[0], 1))
+        diff = lk - ll
+        G = np.empty_like(diff)
+        same = diff == 0.0
+        G[same] = alpha * np.power(ll[same], alpha - 1.0)
+        o = ~same
+        d = diff[o] / ll[o]
+        t = np.where(np.abs(d) < 0.5, np.log1p(d), np.log(lk[o] / ll[o]))
+        G[o] = np.power(ll[o], alpha) * np.expm1(alpha * t) / diff[o]
+        return G
+    p = int(p)
     a = root(lam, p)
     ak = a[:, None]
     al = a[None, :]
     s = np.zeros((a.shape[0], a.shape[0]))
     for i in range(p):
         s += ak ** i * al ** (p - 1 - i)
+    if fn == "root":
+        return 1.0 / s
     return -1.0 / (ak * al * s)
 
 
-def adjoint_column(S: np.ndarray, c: int, w: np.ndarray, p: int):
+def adjoint_column(S: np.ndarray, c: int, w: np.ndarray, p, fn: str = "inv_root"):
     """dL/dS for L = w . (column c of f(S)), on the symmetric part of S."""
     lam, Q = eig(S)
     if lam.min() <= 0.0:
         return np.full(S.shape, np.nan)
     a = Q.T @ w
     b = Q[c, :]
-    M = divided_differences(lam, p) * np.outer(a, b)
+    M = divided_differences(lam, p, fn) * np.outer(a, b)
     return Q @ (0.5 * (M + M.T)) @ Q.T
 
 
-def adjoint(rowptr, colind, vals, n: int, p: int, wvals, cols=None, check: bool = True):
+def adjoint(rowptr, colind, vals, n: int, p, wvals, cols=None, check: bool = True, fn: str = "inv_root"):
     """dL/dA.vals for L = sum(W.vals * X.vals), X = forward(A): every stored
     pair (R_j[k], R_j[l]) of every submatrix receives D_j[k, l]."""
+    check_function(fn, p)
     if check:
         validate(rowptr, colind, n)
     dA = np.zeros(len(colind), dtype=np.float64)
@@ -218,7 +280,7 @@ def adjoint(rowptr, colind, vals, n: int, p: int, wvals, cols=None, check: bool 
         R = submatrix_rows(rowptr, colind, j)
         c = int(np.nonzero(R == j)[0][0])
         S, pos = gather_submatrix(rowptr, colind, vals, R)
-        D = adjoint_column(symmetrise(S), c, wvals[rowptr[j]:rowptr[j + 1]], p)
+        D = adjoint_column(symmetrise(S), c, wvals[rowptr[j]:rowptr[j + 1]], p, fn)
         mask = pos >= 0
         np.add.at(dA, pos[mask], D[mask])
     return dA

@@ -1,5 +1,6 @@
-"""MI355X (gfx950) submatrix-method library: X ~ A^(-1/p) on A's sparsity
-pattern (Lass et al., arXiv:1710.10899), with a Daleckii-Krein adjoint and a
+"""MI355X (gfx950) submatrix-method library: X ~ A^(-1/p) (and the other
+spectral functions lambda^(1/p), lambda^alpha) on A's sparsity pattern (Lass
+et al., arXiv:1710.10899), with a Daleckii-Krein adjoint and a
 mixed-precision form. The computation lives in libsubmat.so (C ABI in
 include/submat.h); this package only binds it.
 """
@@ -13,8 +14,8 @@ from ._lib import (  # noqa: F401
     SubmatError,
 )
 
-__all__ = ["invroot", "invroot_fwd", "invroot_bwd", "invroot_csr", "saved_bytes", "query_status",
-           "time_phases", "InvRoot"]
+__all__ = ["invroot", "invroot_fwd", "invroot_bwd", "invroot_csr", "matfun", "matfun_fwd", "matfun_bwd",
+           "matfun_csr", "saved_bytes", "query_status", "time_phases", "MatFun"]
 
 
 def __getattr__(name):

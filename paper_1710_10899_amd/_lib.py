@@ -29,6 +29,10 @@ SUBMAT_ETOOBIG = -6
 SUBMAT_ESAVED = -7
 SUBMAT_MAX_ORDER = 2048
 
+SUBMAT_FN_INV_ROOT = 0
+SUBMAT_FN_ROOT = 1
+SUBMAT_FN_POWER = 2
+
 SUBMAT_OPT_KAPPA_MAX = 1
 SUBMAT_OPT_USE_GRAPH = 2
 SUBMAT_OPT_SMALL_MAX = 3
@@ -44,7 +48,10 @@ PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "tridiagonal
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
+_D = ctypes.c_double
 SIGNATURES = {
+    "submat_matfun_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P]),
+    "submat_matfun_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P, _P]),
     "submat_invroot_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P]),
     "submat_invroot_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P]),
     "submat_saved_bytes": (_I64, [_P, _P, _I32, _I64, _I32, _I32]),
@@ -55,7 +62,7 @@ SIGNATURES = {
     "submat_strerror": (ctypes.c_char_p, [_I32]),
     "submat_release": (None, []),
     "submat_version": (_I32, []),
-    "submat_time_phases": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P,
+    "submat_time_phases": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P, _P,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
 }
 
@@ -98,6 +105,17 @@ def _check(code: int, where: str) -> None:
 
 
 # ---- same-name wrappers over raw pointers / integers -----------------------
+
+def submat_matfun_fwd(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, saved, stream) -> None:
+    _check(load().submat_matfun_fwd(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, saved,
+                                    stream), "submat_matfun_fwd")
+
+
+def submat_matfun_bwd(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, grad_x, grad_a, saved,
+                      stream) -> None:
+    _check(load().submat_matfun_bwd(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, grad_x, grad_a,
+                                    saved, stream), "submat_matfun_bwd")
+
 
 def submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream) -> None:
     _check(load().submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream),
@@ -149,9 +167,10 @@ def submat_version() -> int:
     return int(load().submat_version())
 
 
-def submat_time_phases(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, grad_x, grad_a, stream) -> dict:
+def submat_time_phases(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, grad_x, grad_a,
+                       stream) -> dict:
     ms = (ctypes.c_double * SUBMAT_NUM_PHASES)()
     nl = (_I32 * SUBMAT_NUM_PHASES)()
-    _check(load().submat_time_phases(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, grad_x, grad_a,
-                                     stream, ms, nl), "submat_time_phases")
+    _check(load().submat_time_phases(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, grad_x,
+                                     grad_a, stream, ms, nl), "submat_time_phases")
     return {PHASES[i]: (ms[i], nl[i]) for i in range(SUBMAT_NUM_PHASES)}

@@ -1,8 +1,15 @@
 """Torch-facing calls of the submatrix-method library.
 
 Tensors supply device memory and the current HIP stream; all computation
-runs in libsubmat.so. ``invroot`` is differentiable with respect to the
-values of A (Daleckii-Krein adjoint in the library).
+runs in libsubmat.so. ``matfun`` (any of the library's spectral functions)
+and ``invroot`` (the inverse p-th root) are differentiable with respect to
+the values of A (Daleckii-Krein adjoint in the library).
+
+Spectral functions, by name -> library code (the parameter is p for the two
+roots, the exponent alpha for a real power):
+  "inv_root"  lambda^(-1/p)   the paper's main case (Sections 3-4)
+  "root"      lambda^(1/p)    positive p-th roots (Section 4, other matrix operations)
+  "power"     lambda^alpha    any real power
 """
 from __future__ import annotations
 
@@ -12,6 +19,18 @@ from . import _lib
 
 _PREC = {"f64": _lib.SUBMAT_PREC_F64, "f32_mixed": _lib.SUBMAT_PREC_F32_MIXED,
          "f64_plain": _lib.SUBMAT_PREC_F64_PLAIN}
+
+
+_FN = {"inv_root": _lib.SUBMAT_FN_INV_ROOT, "root": _lib.SUBMAT_FN_ROOT, "power": _lib.SUBMAT_FN_POWER}
+
+
+def _fn_code(fn) -> int:
+    if isinstance(fn, int):
+        return fn
+    try:
+        return _FN[fn]
+    except KeyError:
+        raise ValueError(f"fn must be one of {sorted(_FN)}") from None
 
 
 def _dtype_code(t: torch.Tensor) -> int:
@@ -54,6 +73,32 @@ def saved_bytes(rowptr, colind, dtype=torch.float64, precision="f64") -> int:
                                    _prec_code(precision))
 
 
+def matfun_fwd(rowptr, colind, vals, fn="inv_root", param: float = 2, precision="f64",
+               saved: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """X.vals with X = f(A) by the submatrix method, on A's pattern."""
+    _check_csr(rowptr, colind, vals)
+    x = torch.empty_like(vals) if out is None else out
+    _lib.submat_matfun_fwd(rowptr.data_ptr(), colind.data_ptr(), vals.data_ptr(), rowptr.numel() - 1,
+                           colind.numel(), _fn_code(fn), float(param), _dtype_code(vals), _prec_code(precision),
+                           x.data_ptr(), saved.data_ptr() if saved is not None else None, _stream())
+    return x
+
+
+def matfun_bwd(rowptr, colind, vals, grad_x, fn="inv_root", param: float = 2, precision="f64",
+               saved: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/dA.vals for L = sum(grad_x * X.vals)."""
+    _check_csr(rowptr, colind, vals)
+    grad_x = grad_x.contiguous()
+    if grad_x.dtype != vals.dtype or grad_x.numel() != vals.numel():
+        raise ValueError("grad_x must match vals in dtype and size")
+    ga = torch.empty_like(vals) if out is None else out
+    _lib.submat_matfun_bwd(rowptr.data_ptr(), colind.data_ptr(), vals.data_ptr(), rowptr.numel() - 1,
+                           colind.numel(), _fn_code(fn), float(param), _dtype_code(vals), _prec_code(precision),
+                           grad_x.data_ptr(), ga.data_ptr(), saved.data_ptr() if saved is not None else None,
+                           _stream())
+    return ga
+
+
 def invroot_fwd(rowptr, colind, vals, p: int = 2, precision="f64", saved: torch.Tensor | None = None,
                 out: torch.Tensor | None = None) -> torch.Tensor:
     _check_csr(rowptr, colind, vals)
@@ -81,32 +126,33 @@ def query_status() -> dict:
     return _lib.submat_query_status(_stream())
 
 
-def time_phases(rowptr, colind, vals, p=2, precision="f64", grad_x=None) -> dict:
+def time_phases(rowptr, colind, vals, p=2, precision="f64", grad_x=None, fn="inv_root") -> dict:
     """Per-phase device time (ms) and launch counts of one forward (and
     adjoint when grad_x is given), direct launches timed with HIP events on
-    the current stream."""
+    the current stream; `p` is the function's parameter."""
     _check_csr(rowptr, colind, vals)
     x = torch.empty_like(vals)
     ga = torch.empty_like(vals) if grad_x is not None else None
     return _lib.submat_time_phases(rowptr.data_ptr(), colind.data_ptr(), vals.data_ptr(), rowptr.numel() - 1,
-                                   colind.numel(), int(p), _dtype_code(vals), _prec_code(precision), x.data_ptr(),
-                                   grad_x.contiguous().data_ptr() if grad_x is not None else None,
+                                   colind.numel(), _fn_code(fn), float(p), _dtype_code(vals), _prec_code(precision),
+                                   x.data_ptr(), grad_x.contiguous().data_ptr() if grad_x is not None else None,
                                    ga.data_ptr() if ga is not None else None, _stream())
 
 
-class InvRoot(torch.autograd.Function):
-    """X.vals = submatrix-method inverse p-th root of A (values on A's
-    pattern); gradients flow to A's values only."""
+class MatFun(torch.autograd.Function):
+    """X.vals = submatrix-method f(A) (values on A's pattern); gradients
+    flow to A's values only."""
 
     @staticmethod
-    def forward(ctx, rowptr, colind, vals, p, precision, keep_eigvecs):
+    def forward(ctx, rowptr, colind, vals, fn, param, precision, keep_eigvecs):
         saved = None
         if keep_eigvecs:
             nb = saved_bytes(rowptr, colind, vals.dtype, precision)
             saved = torch.empty(max(nb, 8), dtype=torch.uint8, device=vals.device)
-        x = invroot_fwd(rowptr, colind, vals, p, precision, saved)
+        x = matfun_fwd(rowptr, colind, vals, fn, param, precision, saved)
         ctx.save_for_backward(rowptr, colind, vals)
-        ctx.p = p
+        ctx.fn = fn
+        ctx.param = param
         ctx.precision = precision
         ctx.saved = saved
         return x
@@ -114,22 +160,34 @@ class InvRoot(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_x):
         rowptr, colind, vals = ctx.saved_tensors
-        ga = invroot_bwd(rowptr, colind, vals, grad_x, ctx.p, ctx.precision, ctx.saved)
+        ga = matfun_bwd(rowptr, colind, vals, grad_x, ctx.fn, ctx.param, ctx.precision, ctx.saved)
         ctx.saved = None
-        return None, None, ga, None, None, None
+        return None, None, ga, None, None, None, None
+
+
+def matfun(rowptr, colind, vals, fn="inv_root", param: float = 2, precision="f64",
+           keep_eigvecs: bool = False) -> torch.Tensor:
+    """Differentiable forward of f(A): returns X's values on A's pattern."""
+    return MatFun.apply(rowptr, colind, vals, _fn_code(fn), float(param), precision, bool(keep_eigvecs))
 
 
 def invroot(rowptr, colind, vals, p: int = 2, precision="f64", keep_eigvecs: bool = False) -> torch.Tensor:
-    """Differentiable forward: returns X's values on A's pattern."""
-    return InvRoot.apply(rowptr, colind, vals, int(p), precision, bool(keep_eigvecs))
+    """Differentiable forward of A^(-1/p): returns X's values on A's pattern."""
+    return MatFun.apply(rowptr, colind, vals, _lib.SUBMAT_FN_INV_ROOT, float(int(p)), precision,
+                        bool(keep_eigvecs))
 
 
 def invroot_csr(a: torch.Tensor, p: int = 2, precision="f64") -> torch.Tensor:
     """X for a torch sparse CSR matrix A, sharing A's index tensors (the
     pattern is reused, Section 3.4)."""
+    return matfun_csr(a, "inv_root", p, precision)
+
+
+def matfun_csr(a: torch.Tensor, fn="inv_root", param: float = 2, precision="f64") -> torch.Tensor:
+    """f(A) for a torch sparse CSR matrix A, on A's pattern and index tensors."""
     if a.layout != torch.sparse_csr:
         raise ValueError("expected a sparse CSR tensor")
     rowptr = a.crow_indices().to(torch.int32)
     colind = a.col_indices().to(torch.int32)
-    x = invroot(rowptr, colind, a.values().contiguous(), p, precision)
+    x = matfun(rowptr, colind, a.values().contiguous(), fn, param, precision)
     return torch.sparse_csr_tensor(a.crow_indices(), a.col_indices(), x, a.shape)

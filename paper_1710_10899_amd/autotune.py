@@ -71,7 +71,7 @@ def time_phases(csr, precision, phases, reps):
     gx = torch.from_numpy(np.ones(csr.nnz)).cuda()
     best = math.inf
     for _ in range(reps):
-        ph = api.time_phases(rp, ci, va, 2, precision, grad_x=gx)
+        ph = api.time_phases(rp, ci, va, 2, precision, grad_x=gx, fn="inv_root")
         best = min(best, sum(ph[k][0] for k in phases if k in ph))
     return best
 

@@ -282,7 +282,7 @@ enum Phase { PH_RESET = 0, PH_SMALL, PH_GATHER, PH_TRIDIAG, PH_EIG, PH_ORTH, PH_
 struct Call {
   const void* vals;
   int vdtype;
-  int p;
+  SpecFn fn;
   int precision;
   void* x;          // forward output
   const void* gx;   // backward input
@@ -364,7 +364,7 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
   a.escr = P.escr.p;
   a.flags = (c.saved ? (int32_t*)(c.saved + P.saved_bytes - 4 * (int64_t)P.large_items.size()) + g_first
                      : P.flags.p + (g_first - P.chunks[chunk].start));
-  a.p = c.p;
+  a.fn = c.fn;
   a.kappa_max = g_opt.kappa_max;
   a.cluster_tol = g_opt.cluster_tol;
   a.x = c.x;
@@ -425,7 +425,7 @@ int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& t
     sa.vals = c.vals;
     sa.vdtype = c.vdtype;
     sa.cidx = P.d_c.p;
-    sa.p = c.p;
+    sa.fn = c.fn;
     sa.mixed = mixed;
     sa.kappa_max = g_opt.kappa_max;
     sa.x = c.bwd ? nullptr : c.x;
@@ -466,8 +466,15 @@ int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& t
   return SUBMAT_OK;
 }
 
+uintptr_t fn_alpha_bits(const SpecFn& f) {
+  uint64_t b = 0;
+  std::memcpy(&b, &f.alpha, sizeof(b));
+  return (uintptr_t)b;
+}
+
 int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
-  std::vector<uintptr_t> key = {(uintptr_t)c.vals, (uintptr_t)c.vdtype, (uintptr_t)c.p, (uintptr_t)c.precision,
+  std::vector<uintptr_t> key = {(uintptr_t)c.vals, (uintptr_t)c.vdtype, (uintptr_t)c.fn.kind, (uintptr_t)c.fn.p,
+                                fn_alpha_bits(c.fn), (uintptr_t)c.precision,
                                 (uintptr_t)c.x, (uintptr_t)c.gx, (uintptr_t)c.ga, (uintptr_t)c.saved,
                                 (uintptr_t)c.bwd, (uintptr_t)(g_opt.kappa_max * 1e3), (uintptr_t)(g_opt.cluster_tol * 1e12),
                                 (uintptr_t)g_opt.tune_gen};
@@ -507,14 +514,30 @@ int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
   return SUBMAT_OK;
 }
 
-int check_args(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz, int32_t p,
+int check_args(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                int32_t dtype, int32_t precision) {
   if (!rowptr || !colind || !vals) return SUBMAT_EINVAL;
-  if (n < 1 || nnz < n || p < 1) return SUBMAT_EINVAL;
+  if (n < 1 || nnz < n) return SUBMAT_EINVAL;
   if (dtype != SUBMAT_F64 && dtype != SUBMAT_F32) return SUBMAT_EINVAL;
   if (precision < SUBMAT_PREC_F64 || precision > SUBMAT_PREC_F64_PLAIN) return SUBMAT_EINVAL;
   if (nnz > (int64_t)INT32_MAX) return SUBMAT_EINVAL;
   return SUBMAT_OK;
+}
+
+// Function code and parameter -> SpecFn; root orders are int32 integers
+// >= 1, exponents finite.
+int make_fn(int32_t kind, double param, SpecFn* out) {
+  if (kind == SUBMAT_FN_INV_ROOT || kind == SUBMAT_FN_ROOT) {
+    if (!(param >= 1.0 && param <= (double)INT32_MAX) || param != std::floor(param)) return SUBMAT_EINVAL;
+    *out = SpecFn{kind, (int)param, 0.0};
+    return SUBMAT_OK;
+  }
+  if (kind == SUBMAT_FN_POWER) {
+    if (!std::isfinite(param)) return SUBMAT_EINVAL;
+    *out = SpecFn{kind, 1, param};
+    return SUBMAT_OK;
+  }
+  return SUBMAT_EINVAL;
 }
 
 int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, Call& c, void* stream,
@@ -545,25 +568,43 @@ int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nn
 // ======================================================================= ABI
 extern "C" {
 
-int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
-                       int32_t p, int32_t dtype, int32_t precision, void* x_vals, void* saved, void* stream) {
-  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
+int submat_matfun_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                      int32_t fn, double param, int32_t dtype, int32_t precision, void* x_vals, void* saved,
+                      void* stream) {
+  SpecFn f{};
+  int rc = check_args(rowptr, colind, vals, n, nnz, dtype, precision);
+  if (!rc) rc = make_fn(fn, param, &f);
   if (rc) return rc;
   if (!x_vals) return SUBMAT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
-  Call c{vals, dtype, p, precision, x_vals, nullptr, nullptr, (char*)saved, false};
+  Call c{vals, dtype, f, precision, x_vals, nullptr, nullptr, (char*)saved, false};
   return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
+}
+
+int submat_matfun_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                      int32_t fn, double param, int32_t dtype, int32_t precision, const void* grad_x,
+                      void* grad_a, const void* saved, void* stream) {
+  SpecFn f{};
+  int rc = check_args(rowptr, colind, vals, n, nnz, dtype, precision);
+  if (!rc) rc = make_fn(fn, param, &f);
+  if (rc) return rc;
+  if (!grad_x || !grad_a) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Call c{vals, dtype, f, precision, nullptr, grad_x, grad_a, (char*)saved, true};
+  return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
+}
+
+int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                       int32_t p, int32_t dtype, int32_t precision, void* x_vals, void* saved, void* stream) {
+  return submat_matfun_fwd(rowptr, colind, vals, n, nnz, SUBMAT_FN_INV_ROOT, (double)p, dtype, precision, x_vals,
+                           saved, stream);
 }
 
 int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                        int32_t p, int32_t dtype, int32_t precision, const void* grad_x, void* grad_a,
                        const void* saved, void* stream) {
-  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
-  if (rc) return rc;
-  if (!grad_x || !grad_a) return SUBMAT_EINVAL;
-  std::lock_guard<std::mutex> lk(g_mu);
-  Call c{vals, dtype, p, precision, nullptr, grad_x, grad_a, (char*)saved, true};
-  return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
+  return submat_matfun_bwd(rowptr, colind, vals, n, nnz, SUBMAT_FN_INV_ROOT, (double)p, dtype, precision, grad_x,
+                           grad_a, saved, stream);
 }
 
 int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, int32_t dtype,
@@ -673,21 +714,23 @@ void submat_release(void) {
   g_plans.clear();
 }
 
-int32_t submat_version(void) { return 110; }
+int32_t submat_version(void) { return 120; }
 
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
-                       int32_t p, int32_t dtype, int32_t precision, void* x_vals, const void* grad_x, void* grad_a,
-                       void* stream, double* phase_ms, int32_t* phase_launches) {
-  int rc = check_args(rowptr, colind, vals, n, nnz, p, dtype, precision);
+                       int32_t fn, double param, int32_t dtype, int32_t precision, void* x_vals,
+                       const void* grad_x, void* grad_a, void* stream, double* phase_ms, int32_t* phase_launches) {
+  SpecFn f{};
+  int rc = check_args(rowptr, colind, vals, n, nnz, dtype, precision);
+  if (!rc) rc = make_fn(fn, param, &f);
   if (rc) return rc;
   if (!x_vals || !phase_ms || !phase_launches) return SUBMAT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
   Timer tm;
-  Call c{vals, dtype, p, precision, x_vals, nullptr, nullptr, nullptr, false};
+  Call c{vals, dtype, f, precision, x_vals, nullptr, nullptr, nullptr, false};
   rc = run_call(rowptr, colind, n, nnz, c, stream, &tm);
   if (rc) return rc;
   if (grad_x && grad_a) {
-    Call cb{vals, dtype, p, precision, nullptr, grad_x, grad_a, nullptr, true};
+    Call cb{vals, dtype, f, precision, nullptr, grad_x, grad_a, nullptr, true};
     rc = run_call(rowptr, colind, n, nnz, cb, stream, &tm);
     if (rc) return rc;
   }

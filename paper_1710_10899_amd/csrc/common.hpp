@@ -31,16 +31,55 @@ __device__ __forceinline__ double root_p(double lam, int p) {
   return pow(lam, 1.0 / (double)p);
 }
 
-// Divided difference of f(x) = x^(-1/p) at lambda_k, lambda_l written in
-// alpha = lambda^(1/p): -1 / (a_k a_l sum_{i<p} a_k^i a_l^(p-1-i)).
-// Free of cancellation, and equal to f'(lambda) when a_k == a_l.
-__device__ __forceinline__ double divdiff(double ak, double al, int p) {
+// The spectral functions (inverse p-th root of Sections 3-4; p-th root and
+// real power of the subsection on other matrix operations), evaluated in
+// FP64 whatever the storage type.
+__device__ __forceinline__ double spec_f(double lam, const SpecFn& f) {
+  if (f.kind == FN_ROOT) return root_p(lam, f.p);
+  if (f.kind == FN_POWER) return pow(lam, f.alpha);
+  return inv_root_p(lam, f.p);
+}
+
+// Per-eigenvalue node from which the divided differences work:
+// alpha = lambda^(1/p) for the two root functions, lambda itself for a real
+// power.
+__device__ __forceinline__ double spec_node(double lam, const SpecFn& f) {
+  return f.kind == FN_POWER ? lam : root_p(lam, f.p);
+}
+
+// Divided difference G = (f(lambda_k) - f(lambda_l)) / (lambda_k - lambda_l),
+// f'(lambda) when equal, from the nodes of spec_node, in forms without
+// cancellation:
+//   inverse root: -1 / (a_k a_l h),  h = sum_{i<p} a_k^i a_l^(p-1-i)
+//   root:          1 / h            (a_k - a_l = (a_k^p - a_l^p) / h)
+//   power:         lambda_l^alpha expm1(alpha t) / (lambda_k - lambda_l),
+//                  t = log(lambda_k / lambda_l), since
+//                  lambda_k^alpha = lambda_l^alpha exp(alpha t); t is taken
+//                  as log1p(d), d = (lambda_k - lambda_l) / lambda_l, for
+//                  |d| < 1/2 (exact difference, full relative accuracy of a
+//                  small t) and as the log of the ratio otherwise (where
+//                  log1p of a d near -1 would lose digits).
+// The power form is a separate instantiation (POW) in the kernels, so that
+// its transcendental calls do not raise the register count of the others.
+__device__ __forceinline__ double root_divdiff(double xk, double xl, const SpecFn& f) {
   double h = 1.0, alp = 1.0;
-  for (int q = 1; q < p; ++q) {
-    alp *= al;
-    h = ak * h + alp;
+  for (int q = 1; q < f.p; ++q) {
+    alp *= xl;
+    h = xk * h + alp;
   }
-  return -1.0 / (ak * al * h);
+  return f.kind == FN_ROOT ? 1.0 / h : -1.0 / (xk * xl * h);
+}
+// pwl = lambda_l^alpha, formed once per eigenvalue by the caller.
+__device__ __forceinline__ double power_divdiff(double xk, double xl, double pwl, double alpha) {
+  const double diff = xk - xl;
+  if (diff == 0.0) return alpha * pwl / xl;
+  const double d = diff / xl;
+  const double t = fabs(d) < 0.5 ? log1p(d) : log(xk / xl);
+  return pwl * expm1(alpha * t) / diff;
+}
+template <bool POW>
+__device__ __forceinline__ double spec_divdiff(double xk, double xl, double pwl, const SpecFn& f) {
+  return POW ? power_divdiff(xk, xl, pwl, f.alpha) : root_divdiff(xk, xl, f);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -32,6 +32,14 @@ hipError_t launch_fill_zero(void* ptr, int64_t bytes, hipStream_t s);
 hipError_t launch_reset_status(int64_t* status, int32_t* counters, int ncounters, hipStream_t s);
 
 // ---- one-wavefront Jacobi path (small.hip) ----
+// Spectral function applied to every submatrix (codes match the ABI's).
+enum FnKind : int { FN_INV_ROOT = 0, FN_ROOT = 1, FN_POWER = 2 };
+struct SpecFn {
+  int kind;      // FnKind
+  int p;         // root order (the two root functions)
+  double alpha;  // exponent (real power)
+};
+
 struct SmallArgs {
   const int32_t* rowptr;
   const int32_t* colind;
@@ -41,7 +49,7 @@ struct SmallArgs {
   const int32_t* cidx;   // c_j per column
   int n_items;
   int mmax;              // largest m among items
-  int p;
+  SpecFn fn;
   int mixed;             // 1: FP32 bulk with FP64 redo of flagged submatrices
   double kappa_max;
   void* x;               // forward output (nullptr in backward)
@@ -79,7 +87,7 @@ struct LargeArgs {
   void* tau;
   void* escr;             // scratch of the eigensolver and the back-transformation
   int32_t* flags;         // per item: bit0 nonpositive, bit1 fallback, bit2 unconverged
-  int p;
+  SpecFn fn;
   double kappa_max;
   double cluster_tol;     // relative eigenvalue gap below which inverse iteration is used
   int lds_limit;          // device limit on LDS bytes per workgroup

@@ -1131,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
     const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
     const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
-    for (int q = tid; q < m; q += kBlock) wv[q] = inv_root_p((double)lam[q], a.p) * (double)Q[(int64_t)q * ld + c];
+    for (int q = tid; q < m; q += kBlock) wv[q] = spec_f((double)lam[q], a.fn) * (double)Q[(int64_t)q * ld + c];
     __syncthreads();
     VT* x = (VT*)a.x + a0;
     for (int r = tid; r < m; r += kBlock) {
@@ -1146,7 +1146,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
 // a = Q^T w, b = Q[c,:]^T, Ms = (G o (a b^T + b a^T))/2, T1 = Q Ms,
 // D = T1 Q^T (lower tiles; D is symmetric), then every stored pair
 // (R[k], R[l]) at position q receives D[max(k,l)][min(k,l)].
-template <class T, class VT>
+template <class T, class VT, bool POW>
 __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
@@ -1177,7 +1177,7 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
       R[i] = a.colind[a0 + i];
       w[i] = (double)gx[i];
       bv[i] = (double)Q[(int64_t)i * ld + c];
-      alv[i] = root_p((double)lam[i], a.p);
+      alv[i] = spec_node((double)lam[i], a.fn);
     }
     __syncthreads();
     for (int pc = wv; pc < m; pc += kBigNW) {
@@ -1187,9 +1187,14 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
       if (lane == 0) av[pc] = part;
     }
     __syncthreads();
+    if (POW) {  // lambda^alpha per eigenvalue, into w (no longer needed)
+      for (int i = tid; i < m; i += kBigBlock) w[i] = pow(alv[i], a.fn.alpha);
+      __syncthreads();
+    }
     for (int l = wv; l < m; l += kBigNW) {
+      const double pwl = POW ? w[l] : 0.0;
       for (int pr = lane; pr < m; pr += kWave) {
-        const double g = divdiff(alv[pr], alv[l], a.p);
+        const double g = spec_divdiff<POW>(alv[pr], alv[l], pwl, a.fn);
         Ms[(int64_t)l * ld + pr] = (T)(0.5 * g * (av[pr] * bv[l] + av[l] * bv[pr]));
       }
     }
@@ -1292,15 +1297,21 @@ hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T, bool POW>
+static void dispatch_adjoint(const LargeArgs& a, size_t lds, hipStream_t s) {
+  SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<T, VT, POW>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
+}
+
 hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   const size_t base = ((size_t)(a.max_m + 1) / 2 + 1) * 8 + vec_lds(a, 4, 8);
+  const bool pw = a.fn.kind == FN_POWER;
   if (a.fp64) {
     const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(double);
-    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<double, VT>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
+    pw ? dispatch_adjoint<double, true>(a, lds, s) : dispatch_adjoint<double, false>(a, lds, s);
   } else {
     const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(float);
-    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<float, VT>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
+    pw ? dispatch_adjoint<float, true>(a, lds, s) : dispatch_adjoint<float, false>(a, lds, s);
   }
   return hipGetLastError();
 }

@@ -146,10 +146,10 @@ __device__ bool jacobi_small(T* A, T* V, int m, double* lam) {
 
 // x_seg[r] = sum_p V[r][p] f(lambda_p) V[c][p]
 template <class T, class VT, int MMAX>
-__device__ void finish_forward(const T* V, SmallShared<MMAX>& sh, int m, int c, int p, bool bad, VT* x_seg) {
+__device__ void finish_forward(const T* V, SmallShared<MMAX>& sh, int m, int c, const SpecFn& fn, bool bad, VT* x_seg) {
   constexpr int LD = MMAX + 1;
   const int lane = threadIdx.x;
-  if (lane < m) sh.aa[lane] = inv_root_p(sh.lam[lane], p) * (double)V[lane * LD + c];
+  if (lane < m) sh.aa[lane] = spec_f(sh.lam[lane], fn) * (double)V[lane * LD + c];
   __syncthreads();
   if (lane < m) {
     double s = 0.0;
@@ -163,8 +163,8 @@ __device__ void finish_forward(const T* V, SmallShared<MMAX>& sh, int m, int c, 
 // every stored pair (R[k], R[l]) at position q gets ga[q] += D[k][l].
 // The symmetric middle factor Ms is formed in LDS, then D is produced one
 // column at a time (y = Ms V[k, :]^T, D[:, k] = V y) and scattered.
-template <class T, class VT, int MMAX>
-__device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c, int p, bool bad,
+template <class T, class VT, int MMAX, bool POW>
+__device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c, const SpecFn& fn, bool bad,
                                 const VT* __restrict__ w_seg, VT* __restrict__ ga,
                                 const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind) {
   constexpr int LD = MMAX + 1;
@@ -176,18 +176,20 @@ __device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c,
   if (lane < m) {
     for (int r = 0; r < m; ++r) a_l = fma((double)V[lane * LD + r], sh.bb[r], a_l);
     b_l = (double)V[lane * LD + c];
-    al_l = root_p(sh.lam[lane], p);
+    al_l = spec_node(sh.lam[lane], fn);
   }
   __syncthreads();
   if (lane < m) {
     sh.aa[lane] = a_l;
     sh.bb[lane] = b_l;
     sh.al[lane] = al_l;
+    if (POW) sh.yv[lane] = pow(al_l, fn.alpha);  // lambda^alpha; yv is free until the columns of D
   }
   __syncthreads();
   if (lane < m) {
     for (int l = 0; l < m; ++l)
-      Ms[l * LD + lane] = 0.5 * divdiff(al_l, sh.al[l], p) * (a_l * sh.bb[l] + sh.aa[l] * b_l);
+      Ms[l * LD + lane] =
+          0.5 * spec_divdiff<POW>(al_l, sh.al[l], POW ? sh.yv[l] : 0.0, fn) * (a_l * sh.bb[l] + sh.aa[l] * b_l);
   }
   __syncthreads();
   for (int k = 0; k < m; ++k) {
@@ -213,7 +215,8 @@ __device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c,
   }
 }
 
-template <class VT, int MMAX, bool BWD>
+// BWD: adjoint instead of forward; POW: the adjoint of a real power
+template <class VT, int MMAX, bool BWD, bool POW>
 __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
   __shared__ SmallShared<MMAX> sh;
   const VT* vals = (const VT*)args.vals;
@@ -238,10 +241,10 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
       const bool flagged = !conv || !(lmin > 0.0) || lmax > args.kappa_max * lmin;
       if (!flagged) {
         if (BWD)
-          finish_backward<float, VT, MMAX>(V, sh, m, c, args.p, false, (const VT*)args.gx + a0,
+          finish_backward<float, VT, MMAX, POW>(V, sh, m, c, args.fn, false, (const VT*)args.gx + a0,
                                            (VT*)args.ga, args.rowptr, args.colind);
         else
-          finish_forward<float, VT, MMAX>(V, sh, m, c, args.p, false, (VT*)args.x + a0);
+          finish_forward<float, VT, MMAX>(V, sh, m, c, args.fn, false, (VT*)args.x + a0);
         done = true;
       } else if (lane == 0) {
         atomicAdd((unsigned long long*)&args.status[ST_FALLBACK], 1ull);
@@ -261,33 +264,37 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
         if (!conv) atomicAdd((unsigned long long*)&args.status[ST_UNCONV], 1ull);
       }
       if (BWD)
-        finish_backward<double, VT, MMAX>(V, sh, m, c, args.p, bad, (const VT*)args.gx + a0,
+        finish_backward<double, VT, MMAX, POW>(V, sh, m, c, args.fn, bad, (const VT*)args.gx + a0,
                                           (VT*)args.ga, args.rowptr, args.colind);
       else
-        finish_forward<double, VT, MMAX>(V, sh, m, c, args.p, bad, (VT*)args.x + a0);
+        finish_forward<double, VT, MMAX>(V, sh, m, c, args.fn, bad, (VT*)args.x + a0);
     }
   }
 }
 
-template <class VT, bool BWD>
+template <class VT, bool BWD, bool POW>
 static hipError_t dispatch_small(const SmallArgs& a, hipStream_t s) {
   const dim3 grid(a.grid), block(64);
   if (a.mmax <= 16)
-    hipLaunchKernelGGL((k_small<VT, 16, BWD>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_small<VT, 16, BWD, POW>), grid, block, 0, s, a);
   else if (a.mmax <= 32)
-    hipLaunchKernelGGL((k_small<VT, 32, BWD>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_small<VT, 32, BWD, POW>), grid, block, 0, s, a);
   else
-    hipLaunchKernelGGL((k_small<VT, 64, BWD>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_small<VT, 64, BWD, POW>), grid, block, 0, s, a);
   return hipGetLastError();
+}
+
+template <class VT>
+static hipError_t dispatch_small_fn(const SmallArgs& a, hipStream_t s) {
+  if (a.gx == nullptr) return dispatch_small<VT, false, false>(a, s);
+  if (a.fn.kind == FN_POWER) return dispatch_small<VT, true, true>(a, s);
+  return dispatch_small<VT, true, false>(a, s);
 }
 
 hipError_t launch_small(const SmallArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.mmax > 64) return hipErrorInvalidValue;
-  const bool bwd = a.gx != nullptr;
-  if (a.vdtype == 0)
-    return bwd ? dispatch_small<double, true>(a, s) : dispatch_small<double, false>(a, s);
-  return bwd ? dispatch_small<float, true>(a, s) : dispatch_small<float, false>(a, s);
+  return a.vdtype == 0 ? dispatch_small_fn<double>(a, s) : dispatch_small_fn<float>(a, s);
 }
 
 }  // namespace submat

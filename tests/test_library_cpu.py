@@ -49,7 +49,7 @@ def test_binding_covers_header():
 def test_version_strerror_options_without_gpu():
     from paper_1710_10899_amd import _lib
     _lib.load()
-    assert _lib.submat_version() == 110
+    assert _lib.submat_version() == 120
     assert _lib.submat_strerror(-3) == "diagonal entry not stored"
     assert _lib.submat_strerror(0) == "ok"
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_KAPPA_MAX) == 1e5
@@ -81,6 +81,16 @@ def test_invalid_arguments_rejected_before_any_device_work():
     with pytest.raises(_lib.SubmatError) as e:
         _lib.submat_invroot_bwd(8, 8, 8, 4, 2, 2, 0, 0, 8, 8, None, None)  # nnz < n
     assert e.value.code == _lib.SUBMAT_EINVAL
+    # spectral function code and parameter
+    for fn, param in ((_lib.SUBMAT_FN_ROOT, 0.0), (_lib.SUBMAT_FN_ROOT, 2.5), (_lib.SUBMAT_FN_INV_ROOT, -1.0),
+                      (_lib.SUBMAT_FN_ROOT, 3e9), (_lib.SUBMAT_FN_POWER, float("inf")),
+                      (_lib.SUBMAT_FN_POWER, float("nan")), (3, 2.0), (-1, 2.0)):
+        with pytest.raises(_lib.SubmatError) as e:
+            _lib.submat_matfun_fwd(8, 8, 8, 4, 4, fn, param, 0, 0, 8, None, None)
+        assert e.value.code == _lib.SUBMAT_EINVAL, (fn, param)
+        with pytest.raises(_lib.SubmatError) as e:
+            _lib.submat_matfun_bwd(8, 8, 8, 4, 4, fn, param, 0, 0, 8, 8, None, None)
+        assert e.value.code == _lib.SUBMAT_EINVAL, (fn, param)
 
 
 def test_product_path_does_not_touch_oracle():

@@ -4,54 +4,104 @@ import numpy as np
 import pytest
 
 import oracle.submat_oracle as so
+import tests.test_oracle_matfun_pins as mpins
 import tests.test_oracle_pins as pins
 
 
-def _wrong_column(S, c, p):
+def _wrong_column(S, c, fn, p):
     lam, Q = so.eig(S)
     c2 = (c + 1) % S.shape[0]
-    return Q @ (so.inv_root(lam, p) * Q[c2, :]), True
+    return Q @ (so.spectral_function(lam, fn, p) * Q[c2, :]), True
 
 
-def _transposed_q(S, c, p):
+def _transposed_q(S, c, fn, p):
     lam, Q = so.eig(S)
-    return Q.T @ (so.inv_root(lam, p) * Q[c, :]), True
+    return Q.T @ (so.spectral_function(lam, fn, p) * Q[c, :]), True
 
 
-def _positive_root(S, c, p):
+def _positive_root(S, c, fn, p):
     lam, Q = so.eig(S)
     return Q @ (so.root(lam, p) * Q[c, :]), True
 
 
-def _dropped_eig_term(S, c, p):
+def _dropped_eig_term(S, c, fn, p):
     lam, Q = so.eig(S)
-    f = so.inv_root(lam, p)
+    f = so.spectral_function(lam, fn, p)
     f[0] = 0.0
     return Q @ (f * Q[c, :]), True
 
 
-def _no_symmetrise_adjoint(S, c, w, p):
+def _no_symmetrise_adjoint(S, c, w, p, fn="inv_root"):
     lam, Q = so.eig(S)
-    M = so.divided_differences(lam, p) * np.outer(Q.T @ w, Q[c, :])
+    M = so.divided_differences(lam, p, fn) * np.outer(Q.T @ w, Q[c, :])
     return Q @ M @ Q.T
 
 
-def _wrong_b_adjoint(S, c, w, p):
+def _wrong_b_adjoint(S, c, w, p, fn="inv_root"):
     lam, Q = so.eig(S)
-    M = so.divided_differences(lam, p) * np.outer(Q.T @ w, Q[:, c])
+    M = so.divided_differences(lam, p, fn) * np.outer(Q.T @ w, Q[:, c])
     return Q @ (0.5 * (M + M.T)) @ Q.T
 
 
-def _sign_flipped_G(lam, p):
+_ORIG_DD = so.divided_differences
+_ORIG_F = so.spectral_function
+
+
+def _sign_flipped_G(lam, p, fn="inv_root"):
+    if fn != "inv_root":
+        return _ORIG_DD(lam, p, fn)
     a = so.root(lam, p)
     s = sum(a[:, None] ** i * a[None, :] ** (p - 1 - i) for i in range(p))
     return 1.0 / (a[:, None] * a[None, :] * s)
 
 
-def _dropped_G_term(lam, p):
+def _dropped_G_term(lam, p, fn="inv_root"):
+    if fn != "inv_root":
+        return _ORIG_DD(lam, p, fn)
     a = so.root(lam, p)
     s = sum(a[:, None] ** i * a[None, :] ** (p - 1 - i) for i in range(max(p - 1, 1)))
     return -1.0 / (a[:, None] * a[None, :] * s)
+
+
+# mistakes in the other spectral functions
+
+
+def _root_G_sign_flipped(lam, p, fn="inv_root"):
+    G0 = _ORIG_DD(lam, p, fn)
+    return -G0 if fn == "root" else G0
+
+
+def _root_G_as_inverse_root(lam, p, fn="inv_root"):
+    return _ORIG_DD(lam, p, "inv_root" if fn == "root" else fn)
+
+
+def _power_G_unscaled(lam, p, fn="inv_root"):
+    G0 = _ORIG_DD(lam, p, fn)
+    if fn != "power":
+        return G0
+    return G0 / np.power(lam[None, :], float(p))
+
+
+def _power_G_log_not_log1p(lam, p, fn="inv_root"):
+    if fn != "power":
+        return _ORIG_DD(lam, p, fn)
+    alpha = float(p)
+    lk, ll = lam[:, None] * np.ones((1, lam.size)), lam[None, :] * np.ones((lam.size, 1))
+    diff = lk - ll
+    G = alpha * np.power(ll, alpha - 1.0)
+    o = diff != 0
+    G[o] = np.power(ll[o], alpha) * np.expm1(alpha * np.log(diff[o] / ll[o] + 2.0)) / diff[o]
+    return G
+
+
+def _root_f_is_inverse_root(lam, fn, param):
+    return _ORIG_F(lam, "inv_root" if fn == "root" else fn, param)
+
+
+def _power_f_reciprocal_exponent(lam, fn, param):
+    if fn != "power":
+        return _ORIG_F(lam, fn, param)
+    return np.power(lam, 1.0 / float(param))
 
 
 _ORIG_GATHER = so.gather_submatrix
@@ -86,6 +136,23 @@ ADJOINT_PINS = [
 ]
 
 
+MATFUN_FORWARD_PINS = [
+    lambda: mpins.test_power_one_reproduces_A(),
+    lambda: mpins.test_power_two_is_A_squared_on_the_pattern(),
+    lambda: mpins.test_root2_of_dense_matrix_is_sqrtm(),
+    lambda: mpins.test_block_diagonal_root_powers_back_to_A(3, True),
+    lambda: mpins.test_dense_real_power_matches_schur_pade(2.5),
+]
+
+MATFUN_ADJOINT_PINS = [
+    lambda: mpins.test_divided_differences_high_precision("root", 2),
+    lambda: mpins.test_divided_differences_high_precision("power", 0.7),
+    lambda: mpins.test_adjoint_power_one_is_symmetrised_upstream(),
+    lambda: mpins.test_adjoint_root2_sylvester(),
+    lambda: mpins.test_matfun_adjoint_central_finite_differences("power", -1.3),
+]
+
+
 def _some_pin_fails(pin_list):
     failures = 0
     for pin in pin_list:
@@ -98,8 +165,27 @@ def _some_pin_fails(pin_list):
 
 @pytest.mark.parametrize("mutant", [_wrong_column, _transposed_q, _positive_root, _dropped_eig_term])
 def test_forward_mutants_are_caught(monkeypatch, mutant):
-    monkeypatch.setattr(so, "column_of_inverse_root", mutant)
+    monkeypatch.setattr(so, "column_of_function", mutant)
     assert _some_pin_fails(FORWARD_PINS) >= 1
+
+
+@pytest.mark.parametrize("mutant", [_wrong_column, _transposed_q, _dropped_eig_term])
+def test_forward_mutants_are_caught_by_other_function_pins(monkeypatch, mutant):
+    monkeypatch.setattr(so, "column_of_function", mutant)
+    assert _some_pin_fails(MATFUN_FORWARD_PINS) >= 1
+
+
+@pytest.mark.parametrize("mutant", [_root_f_is_inverse_root, _power_f_reciprocal_exponent])
+def test_spectral_function_mutants_are_caught(monkeypatch, mutant):
+    monkeypatch.setattr(so, "spectral_function", mutant)
+    assert _some_pin_fails(MATFUN_FORWARD_PINS) >= 1
+
+
+@pytest.mark.parametrize("mutant", [_root_G_sign_flipped, _root_G_as_inverse_root, _power_G_unscaled,
+                                    _power_G_log_not_log1p])
+def test_other_function_divided_difference_mutants_are_caught(monkeypatch, mutant):
+    monkeypatch.setattr(so, "divided_differences", mutant)
+    assert _some_pin_fails(MATFUN_ADJOINT_PINS) >= 1
 
 
 @pytest.mark.parametrize("mutant", [_no_symmetrise_adjoint, _wrong_b_adjoint])

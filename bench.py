@@ -224,6 +224,138 @@ def cpu_baseline(csr, w, p, n_sample=None, fn="inv_root"):
                       f"{cores} processes with single-threaded BLAS, {dt:.2f} s wall"}
 
 
+# ----------------------------------------------------- consumer workloads
+
+
+def spmv_roofline(rp, ci, vals, n, nnz, reps=200):
+    """Average duration of the library's SpMV kernel (one launch per call,
+    on torch's current stream, timed with HIP events around `reps`
+    back-to-back calls) against HBM: algorithmic bytes per launch = values
+    and column indices (12 nnz), row pointers (4 (n + 1)), x read once and
+    y written (16 n)."""
+    import torch
+
+    import paper_1710_10899_amd as sm
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        sm.spmv(rp, ci, vals, x, out=y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sm.spmv(rp, ci, vals, x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"kernel": "k_spmv", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": None, "launch_ms": ms,
+            "bytes_per_launch": nbytes}
+
+
+def run_residual(args):
+    """||X^p A - I||_2 of the submatrix-method result on the named workload:
+    one evaluation = the Lanczos iteration on R^T R in the library."""
+    import torch
+
+    import paper_1710_10899_amd as sm
+    from workloads import generators as G
+    csr = G.make_config(args.workload, kappa=args.kappa)
+    rp = torch.from_numpy(csr.rowptr).cuda()
+    ci = torch.from_numpy(csr.colind).cuda()
+    va = torch.from_numpy(csr.vals).cuda()
+    x = sm.invroot_fwd(rp, ci, va, args.p)
+    for _ in range(args.warmup):
+        norm, steps = sm.residual_norm(rp, ci, va, x, args.p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        norm, steps = sm.residual_norm(rp, ci, va, x, args.p)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    log(f"residual norm {norm:.6e} after {steps} Lanczos steps, {ms:.2f} ms")
+    out = {"metric": "residual-norm evaluations/s (||X^p A - I||_2, Lanczos on R^T R)", "value": 1e3 / ms,
+           "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": WORKLOAD_NAMES[args.workload].format(kappa=csr.meta.get("kappa_target", 0.0),
+                                                                       p=args.p).replace("forward + adjoint",
+                                                                                         "residual metric"),
+                      "n": csr.n, "nnz": csr.nnz, "p": args.p, "lanczos_steps": steps, "residual_norm": norm},
+           "roofline": spmv_roofline(rp, ci, va, csr.n, csr.nnz)}
+    if not args.no_cpu_baseline:
+        from oracle import krylov_oracle as ko
+        xh = x.cpu().numpy()
+        t0 = time.perf_counter()
+        ref = ko.residual_norm_sparse(xh, csr.rowptr, csr.colind, csr.vals, csr.n, args.p)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "evaluations/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one evaluation on the same workload and X (ARPACK on the sparse "
+                                         f"operator, scipy, {dt:.2f} s; value {ref:.6e})"}
+    print(json.dumps(out), flush=True)
+
+
+def run_pcg(args):
+    """A x = b, b = ones, on an ill-conditioned overlap-type matrix of the
+    paper's preconditioning range (384 atoms x 13 = 4992 unknowns, kappa
+    1e5): plain CG and CG on K^T A K y = K^T b with K the submatrix-method
+    A^(-1/2); tolerance 1e-6, at most 2 n iterations. One step = forming K
+    and the preconditioned solve."""
+    import numpy as np
+    import torch
+
+    import paper_1710_10899_amd as sm
+    from workloads import generators as G
+    csr = G.overlap_matrix(n_atoms=384, nbf=13, rcut=4.14, kappa=args.kappa or 1e5, seed=G.BASE_SEED + 60)
+    rp = torch.from_numpy(csr.rowptr).cuda()
+    ci = torch.from_numpy(csr.colind).cuda()
+    va = torch.from_numpy(csr.vals).cuda()
+    b = torch.ones(csr.n, dtype=torch.float64, device="cuda")
+    k = torch.empty_like(va)
+
+    def precond_solve():
+        sm.invroot_fwd(rp, ci, va, 2, out=k)
+        return sm.pcg(rp, ci, va, b, k, tol=1e-6)
+
+    for _ in range(args.warmup):
+        _, info = precond_solve()
+        _, plain = sm.pcg(rp, ci, va, b, None, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = precond_solve()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    _, plain = sm.pcg(rp, ci, va, b, None, tol=1e-6)
+    torch.cuda.synchronize()
+    ms_plain = 1e3 * (time.perf_counter() - t0)
+    log(f"preconditioned: {info['iters']} iterations, {ms:.2f} ms incl. K; plain: {plain['iters']} iterations, "
+        f"{ms_plain:.2f} ms")
+    out = {"metric": "preconditioned CG solves/s (K = submatrix-method A^(-1/2) formed in every solve)",
+           "value": 1e3 / ms, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"overlap-type SPD matrix, 384 atoms x 13 (n={csr.n}), kappa="
+                                  f"{csr.meta.get('kappa_target', 0.0):g}, b = ones, tol 1e-6, max 2n iterations",
+                      "n": csr.n, "nnz": csr.nnz,
+                      "iterations_preconditioned": info["iters"], "iterations_plain": plain["iters"],
+                      "relres_preconditioned": info["relres"], "true_relres_preconditioned": info["true_relres"],
+                      "relres_plain": plain["relres"], "ms_plain_solve": ms_plain},
+           "roofline": spmv_roofline(rp, ci, va, csr.n, csr.nnz)}
+    if not args.no_cpu_baseline:
+        from oracle import krylov_oracle as ko
+        kh = k.cpu().numpy()
+        t0 = time.perf_counter()
+        _, it_o, _ = ko.cg(csr.rowptr, csr.colind, csr.vals, np.ones(csr.n), tol=1e-6, kvals=kh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the preconditioned CG solve on the same system with the same K "
+                                         f"(K formation excluded), scipy sparse products, {it_o} iterations, "
+                                         f"{dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 # --------------------------------------------------------------------- main
 
 
@@ -240,6 +372,9 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="named synthetic workload (2 = the 6656-column overlap matrix the metric is quoted on)")
     ap.add_argument("--kappa", type=float, default=None, help="condition number of the workload (its default if unset)")
+    ap.add_argument("--mode", default="step", choices=["step", "residual", "pcg"],
+                    help="step: forward + adjoint (the headline); residual: the residual metric ||X^p A - I||_2; "
+                         "pcg: CG on A x = b with and without the submatrix-method preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true")
@@ -266,6 +401,12 @@ def main():
 
     _lib.load()
     torch.cuda.set_device(0)
+    if args.mode == "residual":
+        run_residual(args)
+        return
+    if args.mode == "pcg":
+        run_pcg(args)
+        return
     t0 = time.perf_counter()
     csr = G.make_config(args.workload, kappa=args.kappa)
     w = G.upstream_gradient(csr, G.BASE_SEED + args.workload + 100)

@@ -80,6 +80,7 @@ extern "C" {
 #define SUBMAT_EHIP -5     /* a HIP runtime call failed */
 #define SUBMAT_ETOOBIG -6  /* a submatrix order exceeds SUBMAT_MAX_ORDER */
 #define SUBMAT_ESAVED -7   /* `saved` buffer does not belong to this pattern/dtype */
+#define SUBMAT_EBREAKDOWN -8  /* CG breakdown: p^T B p <= 0 or a non-finite residual (operator not SPD) */
 
 /* largest supported submatrix order m_j = nnz of row j */
 #define SUBMAT_MAX_ORDER 2048
@@ -181,6 +182,54 @@ double submat_get_option(int32_t key);
 
 /* Name of a status code (static string). */
 const char* submat_strerror(int32_t code);
+
+/*
+ * ---- Consumers of the result: sparse products, the residual metric and
+ * ---- preconditioned CG. FP64 values only; every array is a device pointer
+ * ---- on the current device; the pattern rules above apply (validated once
+ * ---- per pattern and cached like plans). These calls are synchronous: they
+ * ---- return after the result (and the host outputs) are ready.
+ */
+
+/*
+ * y = M x (trans = 0) or y = M^T x (trans = 1) for the CSR matrix M with
+ * M[i][colind[q]] = vals[q], q in row i. For the column-based X that
+ * submat_matfun_fwd writes (segment j = column j of X), X^T x is trans = 0
+ * and X x is trans = 1. x and y hold n doubles and must not overlap.
+ */
+int submat_spmv(const int32_t* rowptr, const int32_t* colind, const double* vals, int32_t n,
+                int64_t nnz, int32_t trans, const double* x, double* y, void* stream);
+
+/*
+ * Section 4.1 ("Error for random input matrices"): the spectral norm of the
+ * residual R = X^p A - I of an approximate inverse p-th root X (column-based
+ * values on A's pattern), ||R||_2 = sqrt(lambda_max(R^T R)). Lanczos on
+ * R^T R applied matrix-free (R v = X^p (A v) - v, R^T u = A (X^T)^p u - u),
+ * with full reorthogonalisation, from a seeded start vector; stops when the
+ * largest Ritz value changes by at most tol (relative) over 4 steps, or
+ * after max_iter (1..4096) steps. *norm receives ||R||_2, *iters (may be
+ * NULL) the number of Lanczos steps. Workspace: (max_iter + 5) n doubles,
+ * kept per pattern.
+ */
+int submat_residual_norm(const int32_t* rowptr, const int32_t* colind, const double* a_vals,
+                         const double* x_vals, int32_t n, int64_t nnz, int32_t p, int32_t max_iter,
+                         double tol, double* norm, int32_t* iters, void* stream);
+
+/*
+ * Section 4.4 ("Application as preconditioner"): solve A x = b by conjugate
+ * gradients on K^T A K y = K^T b, x = K y, with K the column-based values of
+ * an approximate A^(-1/2) on A's pattern (k_vals; NULL: plain CG on A x = b).
+ * Starts from y = 0; stops when ||r|| <= tol ||K^T b|| for the recursively
+ * updated residual r of the system being solved, or after max_iter
+ * iterations. Outputs: x (n doubles), *iters, *relres = ||r|| / ||K^T b||,
+ * *true_relres = ||b - A x|| / ||b|| (each may be NULL). Returns
+ * SUBMAT_EBREAKDOWN (outputs still written) when the operator is found not
+ * positive definite. Workspace: 6 n doubles (+ nnz with K), kept per pattern.
+ */
+int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_vals,
+               const double* k_vals, int32_t n, int64_t nnz, const double* b, double* x,
+               double tol, int32_t max_iter, int32_t* iters, double* relres, double* true_relres,
+               void* stream);
 
 /* Drop every cached plan, graph and workspace (synchronises the device). */
 void submat_release(void);

@@ -27,6 +27,7 @@ SUBMAT_ENOMEM = -4
 SUBMAT_EHIP = -5
 SUBMAT_ETOOBIG = -6
 SUBMAT_ESAVED = -7
+SUBMAT_EBREAKDOWN = -8
 SUBMAT_MAX_ORDER = 2048
 
 SUBMAT_FN_INV_ROOT = 0
@@ -62,6 +63,11 @@ SIGNATURES = {
     "submat_strerror": (ctypes.c_char_p, [_I32]),
     "submat_release": (None, []),
     "submat_version": (_I32, []),
+    "submat_spmv": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _P]),
+    "submat_residual_norm": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, _I32, _I32, _D, ctypes.POINTER(_D),
+                                            ctypes.POINTER(_I32), _P]),
+    "submat_pcg": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, _P, _P, _D, _I32, ctypes.POINTER(_I32),
+                                  ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
     "submat_time_phases": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P, _P,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
 }
@@ -165,6 +171,32 @@ def submat_release() -> None:
 
 def submat_version() -> int:
     return int(load().submat_version())
+
+
+def submat_spmv(rowptr, colind, vals, n, nnz, trans, x, y, stream) -> None:
+    _check(load().submat_spmv(rowptr, colind, vals, n, nnz, trans, x, y, stream), "submat_spmv")
+
+
+def submat_residual_norm(rowptr, colind, a_vals, x_vals, n, nnz, p, max_iter, tol, stream):
+    norm = _D()
+    iters = _I32()
+    _check(load().submat_residual_norm(rowptr, colind, a_vals, x_vals, n, nnz, p, max_iter, tol,
+                                       ctypes.byref(norm), ctypes.byref(iters), stream), "submat_residual_norm")
+    return norm.value, iters.value
+
+
+def submat_pcg(rowptr, colind, a_vals, k_vals, n, nnz, b, x, tol, max_iter, stream) -> dict:
+    """Returns {"iters", "relres", "true_relres", "breakdown"}; a breakdown
+    is reported in the result, not raised."""
+    iters = _I32()
+    rel = _D()
+    true_rel = _D()
+    rc = load().submat_pcg(rowptr, colind, a_vals, k_vals, n, nnz, b, x, tol, max_iter, ctypes.byref(iters),
+                           ctypes.byref(rel), ctypes.byref(true_rel), stream)
+    if rc not in (SUBMAT_OK, SUBMAT_EBREAKDOWN):
+        _check(rc, "submat_pcg")
+    return {"iters": iters.value, "relres": rel.value, "true_relres": true_rel.value,
+            "breakdown": rc == SUBMAT_EBREAKDOWN}
 
 
 def submat_time_phases(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, grad_x, grad_a,

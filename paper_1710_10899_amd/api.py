@@ -122,6 +122,60 @@ def invroot_bwd(rowptr, colind, vals, grad_x, p: int = 2, precision="f64", saved
     return ga
 
 
+def _check_f64_vec(name, v, n):
+    if not v.is_cuda or v.dtype != torch.float64 or not v.is_contiguous() or v.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 device vector of {n} entries")
+
+
+def spmv(rowptr, colind, vals, x, trans: bool = False, out: torch.Tensor | None = None) -> torch.Tensor:
+    """y = M x (trans=False) or M^T x for the CSR matrix M with row i holding
+    vals[rowptr[i]:rowptr[i+1]] at columns colind[...]. For the column-based
+    result X of matfun_fwd, X^T x is trans=False and X x is trans=True."""
+    _check_csr(rowptr, colind, vals)
+    n = rowptr.numel() - 1
+    if vals.dtype != torch.float64:
+        raise TypeError("spmv takes float64 values")
+    _check_f64_vec("x", x, n)
+    y = torch.empty_like(x) if out is None else out
+    _lib.submat_spmv(rowptr.data_ptr(), colind.data_ptr(), vals.data_ptr(), n, colind.numel(), int(bool(trans)),
+                     x.data_ptr(), y.data_ptr(), _stream())
+    return y
+
+
+def residual_norm(rowptr, colind, a_vals, x_vals, p: int = 2, max_iter: int = 300, tol: float = 1e-10):
+    """||X^p A - I||_2 (Section 4.1) by Lanczos on R^T R in the library;
+    returns (norm, lanczos_steps)."""
+    _check_csr(rowptr, colind, a_vals)
+    _check_csr(rowptr, colind, x_vals)
+    if a_vals.dtype != torch.float64 or x_vals.dtype != torch.float64:
+        raise TypeError("residual_norm takes float64 values")
+    return _lib.submat_residual_norm(rowptr.data_ptr(), colind.data_ptr(), a_vals.data_ptr(), x_vals.data_ptr(),
+                                     rowptr.numel() - 1, colind.numel(), int(p), int(max_iter), float(tol),
+                                     _stream())
+
+
+def pcg(rowptr, colind, a_vals, b, k_vals=None, tol: float = 1e-6, max_iter: int | None = None,
+        out: torch.Tensor | None = None):
+    """Solve A x = b by CG on K^T A K y = K^T b, x = K y (Section 4.4), with
+    K the column-based values of an approximate A^(-1/2) (None: plain CG).
+    max_iter defaults to 2 n. Returns (x, info) with info = {"iters",
+    "relres", "true_relres", "breakdown"}."""
+    _check_csr(rowptr, colind, a_vals)
+    n = rowptr.numel() - 1
+    if a_vals.dtype != torch.float64:
+        raise TypeError("pcg takes float64 values")
+    _check_f64_vec("b", b, n)
+    if k_vals is not None:
+        _check_csr(rowptr, colind, k_vals)
+        if k_vals.dtype != torch.float64:
+            raise TypeError("pcg takes float64 values")
+    x = torch.empty_like(b) if out is None else out
+    info = _lib.submat_pcg(rowptr.data_ptr(), colind.data_ptr(), a_vals.data_ptr(),
+                           k_vals.data_ptr() if k_vals is not None else None, n, colind.numel(), b.data_ptr(),
+                           x.data_ptr(), float(tol), int(2 * n if max_iter is None else max_iter), _stream())
+    return x, info
+
+
 def query_status() -> dict:
     return _lib.submat_query_status(_stream())
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -16,6 +17,7 @@
 #include "../../include/submat.h"
 #include "autotune.hpp"
 #include "kernels.hpp"
+#include "krylov.hpp"
 
 using namespace submat;
 
@@ -274,6 +276,61 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   *out = plan.get();
   g_plans.emplace(key, std::move(plan));
   return SUBMAT_OK;
+}
+
+// ------------------------------------------------------- Krylov patterns
+// Validated pattern (same device check as the plan), the transpose position
+// of every stored entry, and grow-only vectors for the sparse products and
+// Krylov loops. Cached by (device, rowptr, colind, n, nnz), like plans.
+struct KrylovPattern {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int lanes = 64;
+  DevBuf<int32_t> tpos;
+  DevBuf<double> xt;        // transposed values of the preconditioner / root
+  DevBuf<double> vec;       // work vectors
+  DevBuf<double> small;     // Lanczos coefficients and reduction partials
+  DevBuf<uint32_t> ticket;
+  DevBuf<CgState> state;
+};
+std::map<PlanKey, std::unique_ptr<KrylovPattern>> g_kry;
+
+int get_krylov(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, hipStream_t s,
+               DeviceCtx* ctx, KrylovPattern** out) {
+  PlanKey key{ctx->device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
+  auto it = g_kry.find(key);
+  if (it != g_kry.end()) {
+    *out = it->second.get();
+    return SUBMAT_OK;
+  }
+  auto kp = std::make_unique<KrylovPattern>();
+  int rc;
+  {
+    DevBuf<int32_t> m, c;
+    DevBuf<uint32_t> err;
+    if ((rc = m.alloc(n)) || (rc = c.alloc(n)) || (rc = err.alloc(1))) return rc;
+    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(uint32_t), s));
+    HIP_TRY(launch_plan_pattern(rowptr, colind, n, nnz, m.p, c.p, err.p, s));
+    uint32_t h_err = 0;
+    HIP_TRY(hipMemcpyAsync(&h_err, err.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h_err & (PAT_ROWPTR | PAT_RANGE | PAT_ORDER | PAT_ASYM)) return SUBMAT_EPATTERN;
+    if (h_err & PAT_NODIAG) return SUBMAT_ENODIAG;
+  }
+  kp->n = n;
+  kp->nnz = nnz;
+  kp->lanes = spmv_lanes((double)nnz / n);
+  if ((rc = kp->tpos.alloc(nnz)) || (rc = kp->ticket.alloc(1)) || (rc = kp->state.alloc(1))) return rc;
+  HIP_TRY(launch_transpose_positions(rowptr, colind, n, kp->tpos.p, s));
+  HIP_TRY(hipMemsetAsync(kp->ticket.p, 0, sizeof(uint32_t), s));
+  *out = kp.get();
+  g_kry.emplace(key, std::move(kp));
+  return SUBMAT_OK;
+}
+
+template <class T>
+int ensure(DevBuf<T>& b, size_t count) {
+  return b.n >= count ? SUBMAT_OK : b.alloc(count);
 }
 
 // ----------------------------------------------------------- launch sequence
@@ -563,6 +620,162 @@ int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nn
   return run_sequence(*P, ctx, c, s, off);
 }
 
+// ------------------------------------------------------------- Krylov loops
+constexpr uint64_t kLanczosSeed = 0x1710108995ull;
+
+int check_krylov_args(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz) {
+  if (!rowptr || !colind || n < 1 || nnz < n || nnz > (int64_t)INT32_MAX) return SUBMAT_EINVAL;
+  return SUBMAT_OK;
+}
+
+int residual_norm_impl(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* x_vals,
+                       int32_t n, int64_t nnz, int p, int kmax, double tol, double* norm, int32_t* iters,
+                       hipStream_t s) {
+  DeviceCtx* ctx = nullptr;
+  KrylovPattern* K = nullptr;
+  int rc;
+  if ((rc = get_ctx(&ctx)) || (rc = get_krylov(rowptr, colind, n, nnz, s, ctx, &K))) return rc;
+  const int64_t N = n;
+  const int RB = reduction_blocks();
+  if ((rc = ensure(K->vec, (size_t)(kmax + 5) * N)) || (rc = ensure(K->small, (size_t)3 * kmax + 4 + RB)) ||
+      (rc = ensure(K->xt, (size_t)nnz)))
+    return rc;
+  double* V = K->vec.p;                       // (kmax + 1) columns
+  double* a0 = V + (int64_t)(kmax + 1) * N;
+  double* a1 = a0 + N;
+  double* a2 = a1 + N;
+  double* w = a2 + N;
+  double* alpha = K->small.p;                 // kmax
+  double* b2 = alpha + kmax;                  // kmax
+  double* h = b2 + kmax;                      // kmax + 1
+  double* lam_d = h + kmax + 1;               // 1
+  double* tmp = lam_d + 1;                    // 1
+  KrylovScratch ks{tmp + 2, K->ticket.p};
+  HIP_TRY(launch_gather_transpose(K->tpos.p, x_vals, nnz, K->xt.p, s));
+  const SpmvArgs A{rowptr, colind, a_vals, n, K->lanes};
+  const SpmvArgs Xn{rowptr, colind, K->xt.p, n, K->lanes};  // X v (column-based values, transposed)
+  const SpmvArgs Xt{rowptr, colind, x_vals, n, K->lanes};   // X^T v
+  HIP_TRY(hipMemsetAsync(alpha, 0, sizeof(double) * kmax, s));
+  HIP_TRY(launch_random_vector(a0, N, kLanczosSeed, s));
+  HIP_TRY(launch_dot(a0, a0, N, ks, tmp, nullptr, s));
+  HIP_TRY(launch_scale(a0, V, N, nullptr, tmp, 1, s));
+  double lam = 0.0, lam_prev = -1.0;
+  int j = 0;
+  while (j < kmax) {
+    const double* v = V + (int64_t)j * N;
+    // R v = X^p (A v) - v
+    HIP_TRY(launch_spmv(A, v, a0, 0.0, nullptr, nullptr, s));
+    double* src = a0;
+    for (int r = 0; r < p; ++r) {
+      double* dst = src == a0 ? a1 : a0;
+      HIP_TRY(launch_spmv(Xn, src, dst, -1.0, r == p - 1 ? v : nullptr, nullptr, s));
+      src = dst;
+    }
+    double* rv = src;
+    // R^T (R v) = A (X^T)^p (R v) - R v
+    double* pp[2] = {rv == a0 ? a1 : a0, a2};
+    const double* src2 = rv;
+    for (int r = 0; r < p; ++r) {
+      double* dst = pp[r & 1];
+      HIP_TRY(launch_spmv(Xt, src2, dst, 0.0, nullptr, nullptr, s));
+      src2 = dst;
+    }
+    HIP_TRY(launch_spmv(A, src2, w, -1.0, rv, nullptr, s));
+    // full reorthogonalisation (twice) against v_0..v_j; the v_j components
+    // are the Lanczos diagonal
+    for (int pass = 0; pass < 2; ++pass) {
+      HIP_TRY(launch_gemv_t(V, N, j + 1, w, h, s));
+      HIP_TRY(launch_gemv_n_sub(V, N, j + 1, h, w, alpha, j, s));
+    }
+    HIP_TRY(launch_dot(w, w, N, ks, b2 + j, nullptr, s));
+    HIP_TRY(launch_scale(w, V + (int64_t)(j + 1) * N, N, nullptr, b2 + j, 1, s));
+    ++j;
+    if (j % 4 == 0 || j == kmax) {
+      HIP_TRY(launch_tridiag_max(alpha, b2, j, lam_d, s));
+      HIP_TRY(hipMemcpyAsync(&lam, lam_d, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (lam_prev >= 0.0 && std::fabs(lam - lam_prev) <= tol * std::fabs(lam)) break;
+      lam_prev = lam;
+    }
+  }
+  *norm = std::sqrt(lam > 0.0 ? lam : 0.0);
+  if (iters) *iters = j;
+  return SUBMAT_OK;
+}
+
+int pcg_impl(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* k_vals, int32_t n,
+             int64_t nnz, const double* b, double* x, double tol, int max_iter, int32_t* iters, double* relres,
+             double* true_relres, hipStream_t s) {
+  DeviceCtx* ctx = nullptr;
+  KrylovPattern* K = nullptr;
+  int rc;
+  if ((rc = get_ctx(&ctx)) || (rc = get_krylov(rowptr, colind, n, nnz, s, ctx, &K))) return rc;
+  const int64_t N = n;
+  const int RB = reduction_blocks();
+  if ((rc = ensure(K->vec, (size_t)6 * N)) || (rc = ensure(K->small, (size_t)4 + RB))) return rc;
+  if (k_vals && (rc = ensure(K->xt, (size_t)nnz))) return rc;
+  double* r = K->vec.p;
+  double* pv = r + N;
+  double* q = pv + N;
+  double* t = q + N;
+  double* u = t + N;
+  double* y = k_vals ? u + N : x;   // without a preconditioner the iterate is x itself
+  double* sc = K->small.p;          // 2 scalars
+  KrylovScratch ks{sc + 2, K->ticket.p};
+  CgState* st = K->state.p;
+  const int32_t* done = (const int32_t*)((const char*)st + offsetof(CgState, done));
+  CgState init{};
+  init.tol = tol;
+  HIP_TRY(hipMemcpyAsync(st, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+  const SpmvArgs A{rowptr, colind, a_vals, n, K->lanes};
+  SpmvArgs Kn{}, Kt{};
+  if (k_vals) {
+    HIP_TRY(launch_gather_transpose(K->tpos.p, k_vals, nnz, K->xt.p, s));
+    Kn = SpmvArgs{rowptr, colind, K->xt.p, n, K->lanes};  // K v
+    Kt = SpmvArgs{rowptr, colind, k_vals, n, K->lanes};   // K^T v
+    HIP_TRY(launch_spmv(Kt, b, r, 0.0, nullptr, nullptr, s));
+  } else {
+    HIP_TRY(hipMemcpyAsync(r, b, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(launch_cg_start(y, r, pv, N, st, ks, s));
+  CgState h{};
+  HIP_TRY(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int launched = 0;
+  constexpr int kBatch = 32;
+  while (launched < max_iter && !h.done) {
+    const int nb = std::min(kBatch, max_iter - launched);
+    for (int i = 0; i < nb; ++i) {
+      if (k_vals) {
+        HIP_TRY(launch_spmv(Kn, pv, t, 0.0, nullptr, done, s));
+        HIP_TRY(launch_spmv(A, t, u, 0.0, nullptr, done, s));
+        HIP_TRY(launch_spmv(Kt, u, q, 0.0, nullptr, done, s));
+      } else {
+        HIP_TRY(launch_spmv(A, pv, q, 0.0, nullptr, done, s));
+      }
+      HIP_TRY(launch_dot(pv, q, N, ks, &st->pq, done, s));
+      HIP_TRY(launch_cg_update(y, r, pv, q, N, st, ks, s));
+      HIP_TRY(launch_cg_direction(pv, r, N, st, s));
+    }
+    launched += nb;
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.done) break;
+  }
+  if (k_vals) HIP_TRY(launch_spmv(Kn, y, x, 0.0, nullptr, nullptr, s));
+  // true residual ||b - A x|| / ||b||
+  HIP_TRY(launch_spmv(A, x, t, -1.0, b, nullptr, s));
+  HIP_TRY(launch_dot(t, t, N, ks, sc, nullptr, s));
+  HIP_TRY(launch_dot(b, b, N, ks, sc + 1, nullptr, s));
+  double h2[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(h2, sc, sizeof(h2), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters) *iters = h.iters;
+  if (relres) *relres = h.bnorm > 0.0 ? std::sqrt(h.rr) / h.bnorm : 0.0;
+  if (true_relres) *true_relres = h2[1] > 0.0 ? std::sqrt(h2[0] / h2[1]) : 0.0;
+  return h.breakdown ? SUBMAT_EBREAKDOWN : SUBMAT_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -704,6 +917,7 @@ const char* submat_strerror(int32_t code) {
     case SUBMAT_EHIP: return "HIP runtime error";
     case SUBMAT_ETOOBIG: return "submatrix order exceeds SUBMAT_MAX_ORDER";
     case SUBMAT_ESAVED: return "saved buffer does not match";
+    case SUBMAT_EBREAKDOWN: return "CG breakdown (operator not positive definite)";
     default: return "unknown status code";
   }
 }
@@ -712,6 +926,49 @@ void submat_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   (void)hipDeviceSynchronize();
   g_plans.clear();
+  g_kry.clear();
+}
+
+int submat_spmv(const int32_t* rowptr, const int32_t* colind, const double* vals, int32_t n, int64_t nnz,
+                int32_t trans, const double* x, double* y, void* stream) {
+  int rc = check_krylov_args(rowptr, colind, n, nnz);
+  if (rc) return rc;
+  if (!vals || !x || !y || (trans != 0 && trans != 1)) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipStream_t s = (hipStream_t)stream;
+  DeviceCtx* ctx = nullptr;
+  KrylovPattern* K = nullptr;
+  if ((rc = get_ctx(&ctx)) || (rc = get_krylov(rowptr, colind, n, nnz, s, ctx, &K))) return rc;
+  const double* v = vals;
+  if (trans) {
+    if ((rc = ensure(K->xt, (size_t)nnz))) return rc;
+    HIP_TRY(launch_gather_transpose(K->tpos.p, vals, nnz, K->xt.p, s));
+    v = K->xt.p;
+  }
+  HIP_TRY(launch_spmv(SpmvArgs{rowptr, colind, v, n, K->lanes}, x, y, 0.0, nullptr, nullptr, s));
+  return SUBMAT_OK;
+}
+
+int submat_residual_norm(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* x_vals,
+                         int32_t n, int64_t nnz, int32_t p, int32_t max_iter, double tol, double* norm,
+                         int32_t* iters, void* stream) {
+  int rc = check_krylov_args(rowptr, colind, n, nnz);
+  if (rc) return rc;
+  if (!a_vals || !x_vals || !norm || p < 1 || max_iter < 1 || max_iter > 4096 || !(tol >= 0.0)) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return residual_norm_impl(rowptr, colind, a_vals, x_vals, n, nnz, p, max_iter, tol, norm, iters,
+                            (hipStream_t)stream);
+}
+
+int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* k_vals, int32_t n,
+               int64_t nnz, const double* b, double* x, double tol, int32_t max_iter, int32_t* iters,
+               double* relres, double* true_relres, void* stream) {
+  int rc = check_krylov_args(rowptr, colind, n, nnz);
+  if (rc) return rc;
+  if (!a_vals || !b || !x || max_iter < 0 || !(tol > 0.0)) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return pcg_impl(rowptr, colind, a_vals, k_vals, n, nnz, b, x, tol, max_iter, iters, relres, true_relres,
+                  (hipStream_t)stream);
 }
 
 int32_t submat_version(void) { return 120; }

@@ -203,3 +203,91 @@ def test_divided_difference_mutants_are_caught(monkeypatch, mutant):
 def test_gather_mutant_is_caught(monkeypatch):
     monkeypatch.setattr(so, "gather_submatrix", _gather_ignores_pattern)
     assert _some_pin_fails(FORWARD_PINS) >= 1
+
+
+# ---------------------------------------------------------------------------
+# residual metric and conjugate gradients (Sections 4.1 and 4.4)
+
+from oracle import krylov_oracle as ko  # noqa: E402
+import tests.test_oracle_krylov_pins as kpins  # noqa: E402
+
+_ORIG_RES_OP = ko.residual_operator
+_ORIG_ROW_BASED = ko.row_based_matrix
+
+
+def _res_op_one_power_short(xvals, rowptr, colind, avals, n, p):
+    return _ORIG_RES_OP(xvals, rowptr, colind, avals, n, max(p - 1, 1) if p > 1 else p)
+
+
+def _column_based_is_row_based(rowptr, colind, vals, n):
+    return _ORIG_ROW_BASED(rowptr, colind, vals, n)
+
+
+def _cg_beta_from_dq(rowptr, colind, avals, b, tol=1e-6, maxit=None, kvals=None):
+    """CG with beta = rr_new / (d . B d) instead of rr_new / rr."""
+    n = len(rowptr) - 1
+    A = ko.row_based_matrix(rowptr, colind, avals, n)
+    K = ko.column_based_matrix(rowptr, colind, kvals, n) if kvals is not None else None
+    op = (lambda v: K.T @ (A @ (K @ v))) if K is not None else (lambda v: A @ v)
+    rhs = K.T @ b if K is not None else np.asarray(b, dtype=float).copy()
+    maxit = 2 * n if maxit is None else maxit
+    y, r = np.zeros(n), rhs.copy()
+    d, rr = r.copy(), float(r @ r)
+    bnorm, it = np.sqrt(rr), 0
+    if bnorm == 0.0:
+        return np.zeros(n), 0, 0.0
+    while it < maxit:
+        q = op(d)
+        dq = float(d @ q)
+        if not dq > 0.0:
+            break
+        y, r = y + (rr / dq) * d, r - (rr / dq) * q
+        rr_new = float(r @ r)
+        it += 1
+        if np.sqrt(rr_new) <= tol * bnorm:
+            rr = rr_new
+            break
+        d = r + (rr_new / dq) * d
+        rr = rr_new
+    return (K @ y if K is not None else y), it, float(np.sqrt(rr) / bnorm)
+
+
+_ORIG_CG = ko.cg
+
+
+def _cg_rhs_without_kt(rowptr, colind, avals, b, tol=1e-6, maxit=None, kvals=None):
+    """Preconditioned CG with K b instead of K^T b on the right."""
+    if kvals is None:
+        return _ORIG_CG(rowptr, colind, avals, b, tol, maxit, None)
+    n = len(rowptr) - 1
+    K = ko.column_based_matrix(rowptr, colind, kvals, n)
+    b2 = K.T @ np.linalg.lstsq(K.T.toarray(), K @ b, rcond=None)[0]
+    return _ORIG_CG(rowptr, colind, avals, b2, tol, maxit, kvals)
+
+
+RESIDUAL_PINS = [
+    lambda: kpins.test_sparse_residual_norm_equals_dense_definition(2),
+    lambda: kpins.test_residual_norm_diagonal_closed_form(2),
+    lambda: kpins.test_residual_operator_transpose_is_adjoint(),
+    lambda: kpins.test_column_based_matrix_reads_segments_as_columns(),
+]
+
+CG_PINS = [
+    lambda: kpins.test_cg_matches_scipy_iterations_and_solution(1e2),
+    lambda: kpins.test_cg_terminates_in_k_steps_for_k_distinct_eigenvalues(),
+    lambda: kpins.test_exact_preconditioner_converges_in_one_step(),
+    lambda: kpins.test_preconditioned_cg_solves_original_system(),
+]
+
+
+@pytest.mark.parametrize("name,mutant", [("residual_operator", _res_op_one_power_short),
+                                         ("column_based_matrix", _column_based_is_row_based)])
+def test_residual_mutants_are_caught(monkeypatch, name, mutant):
+    monkeypatch.setattr(ko, name, mutant)
+    assert _some_pin_fails(RESIDUAL_PINS) >= 1
+
+
+@pytest.mark.parametrize("mutant", [_cg_beta_from_dq, _cg_rhs_without_kt])
+def test_cg_mutants_are_caught(monkeypatch, mutant):
+    monkeypatch.setattr(ko, "cg", mutant)
+    assert _some_pin_fails(CG_PINS) >= 1

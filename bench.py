@@ -356,6 +356,69 @@ def run_pcg(args):
     print(json.dumps(out), flush=True)
 
 
+def run_error_study(args):
+    """The error study of Section 4.1 on synthetic inputs: random sparse SPD
+    matrices of density 0.05 (random symmetric pattern, N(0,1) values,
+    diagonal shift to an exact condition number kappa), n = 256..4096, kappa = 2..1e3 for p = 1, and
+    p = 2, 3 at kappa = 2; two seeds per point. For each matrix the library
+    forms X and evaluates ||X^p A - I||_2. The oracle (dense residual of its
+    own X) is run beside it on one seed of every point with n <= 1024."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1710_10899_amd as sm
+    from workloads import generators as G
+    sizes = (256, 512, 1024, 2048, 4096)
+    kappas = (2.0, 10.0, 100.0, 1000.0)
+    seeds = (0, 1)
+    rows, parity, t_gpu, t_cpu, cpu_n = [], [], 0.0, 0.0, 0
+    for n in sizes:
+        for kappa in kappas:
+            for sd in seeds:
+                csr = G.random_sparse_spd(n, 0.05, seed=G.BASE_SEED + 700 + 10 * sd + n + int(kappa), kappa=kappa)
+                rp = torch.from_numpy(csr.rowptr).cuda()
+                ci = torch.from_numpy(csr.colind).cuda()
+                va = torch.from_numpy(csr.vals).cuda()
+                for p in ((1, 2, 3) if kappa == 2.0 else (1,)):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    x = sm.invroot_fwd(rp, ci, va, p)
+                    norm, steps = sm.residual_norm(rp, ci, va, x, p)
+                    torch.cuda.synchronize()
+                    t_gpu += time.perf_counter() - t0
+                    rows.append({"n": n, "kappa": kappa, "p": p, "seed": sd, "density": csr.nnz / n / n,
+                                 "m_max": int(csr.row_sizes().max()), "residual": norm, "lanczos_steps": steps})
+                    if sd == 0 and n <= 1024:
+                        t0 = time.perf_counter()
+                        xo, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, n, p, check=False)
+                        ref = oracle.residual_norm(xo, csr.rowptr, csr.colind, csr.vals, n, p)
+                        t_cpu += time.perf_counter() - t0
+                        cpu_n += 1
+                        parity.append(abs(norm - ref) / ref)
+                log(f"n={n} kappa={kappa:g} seed={sd}: " + ", ".join(
+                    f"p={r['p']} {r['residual']:.3e}" for r in rows if r["n"] == n and r["kappa"] == kappa
+                    and r["seed"] == sd))
+    table = {}
+    for r in rows:
+        table.setdefault(f"p={r['p']} kappa={r['kappa']:g}", {}).setdefault(str(r["n"]), []).append(r["residual"])
+    summary = {k: {n_: float(np.mean(v)) for n_, v in d.items()} for k, d in table.items()}
+    out = {"metric": "matrices/s through X and ||X^p A - I||_2 (error study, Section 4.1)",
+           "value": len(rows) / t_gpu, "unit": "matrices/s", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+           "ms_per_step": 1e3 * t_gpu / len(rows), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "random sparse SPD, density 0.05, N(0,1) values shifted to an exact kappa, "
+                                  "n 256-4096, kappa 2-1e3, p 1 (and 2, 3 at kappa 2), 2 seeds",
+                      "mean_residual": summary,
+                      "max_rel_diff_vs_oracle": float(max(parity)) if parity else None,
+                      "oracle_cases": len(parity)},
+           "rows": rows}
+    out["cpu_baseline"] = {"value": cpu_n / t_cpu if t_cpu else None, "unit": "matrices/s", "cores": 1,
+                           "kind": "oracle", "sample": f"{cpu_n} matrices with n <= 1024 (oracle X and dense "
+                                                      f"residual), {t_cpu:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 # --------------------------------------------------------------------- main
 
 
@@ -372,9 +435,10 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="named synthetic workload (2 = the 6656-column overlap matrix the metric is quoted on)")
     ap.add_argument("--kappa", type=float, default=None, help="condition number of the workload (its default if unset)")
-    ap.add_argument("--mode", default="step", choices=["step", "residual", "pcg"],
+    ap.add_argument("--mode", default="step", choices=["step", "residual", "pcg", "error-study"],
                     help="step: forward + adjoint (the headline); residual: the residual metric ||X^p A - I||_2; "
-                         "pcg: CG on A x = b with and without the submatrix-method preconditioner")
+                         "pcg: CG on A x = b with and without the submatrix-method preconditioner; "
+                         "error-study: the residual against n and kappa on random sparse SPD matrices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true")
@@ -406,6 +470,9 @@ def main():
         return
     if args.mode == "pcg":
         run_pcg(args)
+        return
+    if args.mode == "error-study":
+        run_error_study(args)
         return
     t0 = time.perf_counter()
     csr = G.make_config(args.workload, kappa=args.kappa)

@@ -70,3 +70,4 @@ def test_cached_extremes_match_lanczos_on_a_smaller_matrix():
     b = G.shift_to_kappa(csr, 1e4, ext)
     assert abs(a.meta["sigma"] - b.meta["sigma"]) <= 1e-9 * abs(b.meta["sigma"])
     assert abs(b.meta["lmax"] / b.meta["lmin"] - 1e4) <= 1e-6 * 1e4
+

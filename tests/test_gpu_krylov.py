@@ -86,6 +86,24 @@ def test_residual_norm_full_size_workload(gpu_lib):
     assert abs(norm - ref) <= 1e-8 * ref
 
 
+@pytest.mark.parametrize("kappa", [2.0, 100.0])
+def test_residual_norm_on_error_study_matrices(kappa, gpu_lib):
+    """The random sparse SPD inputs of the error study (density 0.05, exact
+    condition number kappa): GPU X and GPU metric against the oracle's X and
+    the dense definition."""
+    import paper_1710_10899_amd as sm
+    csr = G.random_sparse_spd(512, 0.05, seed=G.BASE_SEED + 800, kappa=kappa)
+    check_launch_shapes(csr)
+    for p in (1, 2):
+        banner(f"error-study matrix n=512 kappa={kappa:g} p={p}")
+        rp, ci, va, x = gpu_root(csr, p)
+        norm, _ = sm.residual_norm(rp, ci, va, x, p)
+        xo, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, p)
+        ref = oracle.residual_norm(xo, csr.rowptr, csr.colind, csr.vals, csr.n, p)
+        print(f"kappa={kappa:g} p={p} gpu {norm:.15e} oracle {ref:.15e}", flush=True)
+        assert abs(norm - ref) <= 1e-8 * ref
+
+
 def _near_tie(csr, b, tol, kvals, it):
     """True when the oracle's residual after it-1 or it iterations lies
     within 1% of the threshold (rounding could move the stop by one)."""

@@ -419,6 +419,75 @@ def run_error_study(args):
     print(json.dumps(out), flush=True)
 
 
+def run_refine(args):
+    """Refinement of the submatrix-method inverse (p = 1) on the named
+    workload by Newton-Schulz to ||I - A X||_F / sqrt(n) <= 1e-14; one step
+    = the seed's densification plus all refinement steps. The dominant
+    kernel is the FP64 DGEMM (2 n^3 flops per product, two per step)."""
+    import numpy as np
+    import torch
+
+    import paper_1710_10899_amd as sm
+    from workloads import generators as G
+    csr = G.make_config(args.workload, kappa=args.kappa)
+    n = csr.n
+    rp = torch.from_numpy(csr.rowptr).cuda()
+    ci = torch.from_numpy(csr.colind).cuda()
+    va = torch.from_numpy(csr.vals).cuda()
+    x = sm.invroot_fwd(rp, ci, va, 1)
+    X = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        _, info = sm.refine_inverse(rp, ci, va, x, tol=1e-14, out=X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, info = sm.refine_inverse(rp, ci, va, x, tol=1e-14, out=X)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    # one Newton-Schulz step (two DGEMMs, a copy, the residual) as the
+    # difference of 5 fixed steps and none, timed with HIP events on the
+    # library's stream (torch's current stream)
+    def timed(k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sm.refine_inverse(rp, ci, va, x, max_iter=k, tol=0.0, out=X)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    timed(1)
+    step_ms = (timed(5) - timed(0)) / 5
+    gemm_ms = step_ms / 2
+    tf = 4.0 * n ** 3 / (step_ms / 1e3) / 1e12
+    log(f"refinement: {info['iters']} steps to {info['residual']:.2e} in {ms:.1f} ms; one step {step_ms:.2f} ms "
+        f"({tf:.1f} TFLOP/s)")
+    out = {"metric": "refinements/s (Newton-Schulz on the p = 1 result to ||I - A X||_F / sqrt(n) <= 1e-14)",
+           "value": 1e3 / ms, "unit": "refinements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": WORKLOAD_NAMES[args.workload].format(kappa=csr.meta.get("kappa_target", 0.0),
+                                                                       p=1).replace("forward + adjoint",
+                                                                                    "dense refinement"),
+                      "n": n, "newton_schulz_steps": info["iters"], "final_residual": info["residual"],
+                      "flops_per_step": 4.0 * n ** 3},
+           "roofline": {"kernel": "Newton-Schulz step (two rocBLAS DGEMMs, n x n x n)", "bound": "mfma",
+                        "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+                        "traffic": None, "launch_ms": gemm_ms}}
+    if not args.no_cpu_baseline:
+        import threadpoolctl  # noqa: F401  (reports the BLAS thread count)
+        from oracle import krylov_oracle as ko
+        xh = x.cpu().numpy()
+        t0 = time.perf_counter()
+        ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, xh, tol=0.0, maxit=1)
+        dt = time.perf_counter() - t0
+        info_t = threadpoolctl.threadpool_info()
+        cores = max((d.get("num_threads", 1) for d in info_t), default=1)
+        out["cpu_baseline"] = {"value": 1.0 / (dt * max(info["iters"], 1)), "unit": "refinements/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"one Newton-Schulz step of the oracle (numpy, two dense products) on the "
+                                         f"same workload, {dt:.1f} s, scaled to the GPU's {info['iters']} steps"}
+    print(json.dumps(out), flush=True)
+
+
 # --------------------------------------------------------------------- main
 
 
@@ -435,10 +504,11 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
                     help="named synthetic workload (2 = the 6656-column overlap matrix the metric is quoted on)")
     ap.add_argument("--kappa", type=float, default=None, help="condition number of the workload (its default if unset)")
-    ap.add_argument("--mode", default="step", choices=["step", "residual", "pcg", "error-study"],
+    ap.add_argument("--mode", default="step", choices=["step", "residual", "pcg", "error-study", "refine"],
                     help="step: forward + adjoint (the headline); residual: the residual metric ||X^p A - I||_2; "
                          "pcg: CG on A x = b with and without the submatrix-method preconditioner; "
-                         "error-study: the residual against n and kappa on random sparse SPD matrices")
+                         "error-study: the residual against n and kappa on random sparse SPD matrices; "
+                         "refine: Newton-Schulz refinement of the p = 1 result")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-phases", action="store_true")
@@ -473,6 +543,9 @@ def main():
         return
     if args.mode == "error-study":
         run_error_study(args)
+        return
+    if args.mode == "refine":
+        run_refine(args)
         return
     t0 = time.perf_counter()
     csr = G.make_config(args.workload, kappa=args.kappa)

@@ -81,6 +81,7 @@ extern "C" {
 #define SUBMAT_ETOOBIG -6  /* a submatrix order exceeds SUBMAT_MAX_ORDER */
 #define SUBMAT_ESAVED -7   /* `saved` buffer does not belong to this pattern/dtype */
 #define SUBMAT_EBREAKDOWN -8  /* CG breakdown: p^T B p <= 0 or a non-finite residual (operator not SPD) */
+#define SUBMAT_ENOCONV -9     /* refinement stopped without reaching its tolerance (outputs written) */
 
 /* largest supported submatrix order m_j = nnz of row j */
 #define SUBMAT_MAX_ORDER 2048
@@ -230,6 +231,27 @@ int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_val
                const double* k_vals, int32_t n, int64_t nnz, const double* b, double* x,
                double tol, int32_t max_iter, int32_t* iters, double* relres, double* true_relres,
                void* stream);
+
+/*
+ * Section 4.5 ("Controlling the approximation error"): refine the
+ * submatrix-method inverse (p = 1) with the Newton-Schulz iteration
+ * X_{k+1} = 2 X_k - X_k A X_k seeded with X_0 = X (x_vals, column-based on
+ * A's pattern). I - A X_{k+1} = (I - A X_k)^2, so it converges quadratically
+ * to A^{-1} whenever the spectral radius of I - A X_0 is below 1. The result
+ * leaves A's pattern: x_dense receives the dense row-major n x n iterate
+ * (n^2 doubles, caller-owned, n <= 65536). Stops when ||I - A X_k||_F /
+ * sqrt(n) <= tol (*residual, may be NULL, receives that value for the
+ * returned X; *iters the number of Newton-Schulz steps), after max_iter
+ * steps, or when the residual grows beyond 1e3 times its start (or 1e3),
+ * the last two returning SUBMAT_ENOCONV with the outputs written. Dense
+ * products by rocBLAS DGEMM; workspace 3 n^2 doubles, kept per pattern.
+ * (For p >= 2 the Newton-Schulz step is not stable from a seed that does
+ * not commute with A, so no refinement is offered there.)
+ */
+int submat_refine_inverse(const int32_t* rowptr, const int32_t* colind, const double* a_vals,
+                          const double* x_vals, int32_t n, int64_t nnz, double* x_dense,
+                          int32_t max_iter, double tol, int32_t* iters, double* residual,
+                          void* stream);
 
 /* Drop every cached plan, graph and workspace (synchronises the device). */
 void submat_release(void);

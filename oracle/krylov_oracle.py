@@ -117,3 +117,29 @@ def cg(rowptr, colind, avals, b, tol: float = 1e-6, maxit: int | None = None, kv
         rr = rr_new
     x = K @ y if K is not None else y
     return x, it, float(np.sqrt(rr) / bnorm)
+
+
+def refine_inverse(rowptr, colind, avals, xvals, tol: float = 1e-14, maxit: int = 20):
+    """Section 4.5: refinement of the submatrix-method inverse (p = 1),
+    used as the initial guess of the Newton-Schulz iteration
+    X_{k+1} = 2 X_k - X_k A X_k (so that I - A X_{k+1} = (I - A X_k)^2).
+    Stops when ||I - A X_k||_F / sqrt(n) <= tol, after maxit steps, or when
+    that residual exceeds 1e3 times its start (or 1e3). Returns (dense X,
+    steps, residual of the returned X, converged)."""
+    n = len(rowptr) - 1
+    A = row_based_matrix(rowptr, colind, avals, n).toarray()
+    X = column_based_matrix(rowptr, colind, xvals, n).toarray()
+    I = np.eye(n)
+    k = 0
+    res0 = None
+    while True:
+        T = A @ X
+        res = float(np.linalg.norm(T - I) / np.sqrt(n))
+        if res0 is None:
+            res0 = res
+        if res <= tol:
+            return X, k, res, True
+        if not np.isfinite(res) or res > 1e3 * max(res0, 1.0) or k >= maxit:
+            return X, k, res, False
+        X = 2.0 * X - X @ T
+        k += 1

@@ -28,6 +28,7 @@ SUBMAT_EHIP = -5
 SUBMAT_ETOOBIG = -6
 SUBMAT_ESAVED = -7
 SUBMAT_EBREAKDOWN = -8
+SUBMAT_ENOCONV = -9
 SUBMAT_MAX_ORDER = 2048
 
 SUBMAT_FN_INV_ROOT = 0
@@ -68,6 +69,8 @@ SIGNATURES = {
                                             ctypes.POINTER(_I32), _P]),
     "submat_pcg": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, _P, _P, _D, _I32, ctypes.POINTER(_I32),
                                   ctypes.POINTER(_D), ctypes.POINTER(_D), _P]),
+    "submat_refine_inverse": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, _P, _I32, _D, ctypes.POINTER(_I32),
+                                             ctypes.POINTER(_D), _P]),
     "submat_time_phases": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P, _P,
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32)]),
 }
@@ -197,6 +200,18 @@ def submat_pcg(rowptr, colind, a_vals, k_vals, n, nnz, b, x, tol, max_iter, stre
         _check(rc, "submat_pcg")
     return {"iters": iters.value, "relres": rel.value, "true_relres": true_rel.value,
             "breakdown": rc == SUBMAT_EBREAKDOWN}
+
+
+def submat_refine_inverse(rowptr, colind, a_vals, x_vals, n, nnz, x_dense, max_iter, tol, stream) -> dict:
+    """Returns {"iters", "residual", "converged"}; non-convergence is
+    reported in the result, not raised."""
+    iters = _I32()
+    res = _D()
+    rc = load().submat_refine_inverse(rowptr, colind, a_vals, x_vals, n, nnz, x_dense, max_iter, tol,
+                                      ctypes.byref(iters), ctypes.byref(res), stream)
+    if rc not in (SUBMAT_OK, SUBMAT_ENOCONV):
+        _check(rc, "submat_refine_inverse")
+    return {"iters": iters.value, "residual": res.value, "converged": rc == SUBMAT_OK}
 
 
 def submat_time_phases(rowptr, colind, vals, n, nnz, fn, param, dtype, precision, x_vals, grad_x, grad_a,

@@ -176,6 +176,23 @@ def pcg(rowptr, colind, a_vals, b, k_vals=None, tol: float = 1e-6, max_iter: int
     return x, info
 
 
+def refine_inverse(rowptr, colind, a_vals, x_vals, max_iter: int = 20, tol: float = 1e-14,
+                   out: torch.Tensor | None = None):
+    """Newton-Schulz refinement of the submatrix-method inverse (p = 1)
+    seeded with x_vals (Section 4.5); returns (dense row-major X, info)."""
+    _check_csr(rowptr, colind, a_vals)
+    _check_csr(rowptr, colind, x_vals)
+    if a_vals.dtype != torch.float64 or x_vals.dtype != torch.float64:
+        raise TypeError("refine_inverse takes float64 values")
+    n = rowptr.numel() - 1
+    xd = torch.empty((n, n), dtype=torch.float64, device=a_vals.device) if out is None else out
+    if xd.shape != (n, n) or not xd.is_contiguous() or xd.dtype != torch.float64:
+        raise ValueError("out must be a contiguous float64 n x n tensor")
+    info = _lib.submat_refine_inverse(rowptr.data_ptr(), colind.data_ptr(), a_vals.data_ptr(), x_vals.data_ptr(), n,
+                                      colind.numel(), xd.data_ptr(), int(max_iter), float(tol), _stream())
+    return xd, info
+
+
 def query_status() -> dict:
     return _lib.submat_query_status(_stream())
 

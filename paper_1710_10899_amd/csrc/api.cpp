@@ -1,6 +1,7 @@
 // C-ABI layer: plan cache, size buckets, chunked workspace, launch
 // sequences, hipGraph capture and replay, status counters, phase timing.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -62,6 +63,10 @@ struct DeviceCtx {
   int lds_limit = 65536;
   DevBuf<int64_t> status;      // ST_NSLOTS slots
   std::vector<int64_t> last_status;
+  rocblas_handle blas = nullptr;  // dense products of the refinement, created on first use
+  ~DeviceCtx() {
+    if (blas) (void)rocblas_destroy_handle(blas);
+  }
 };
 std::map<int, std::unique_ptr<DeviceCtx>> g_dev;
 
@@ -292,6 +297,7 @@ struct KrylovPattern {
   DevBuf<double> small;     // Lanczos coefficients and reduction partials
   DevBuf<uint32_t> ticket;
   DevBuf<CgState> state;
+  DevBuf<double> dense;     // refinement: dense A, T = A X, and the next iterate
 };
 std::map<PlanKey, std::unique_ptr<KrylovPattern>> g_kry;
 
@@ -776,6 +782,64 @@ int pcg_impl(const int32_t* rowptr, const int32_t* colind, const double* a_vals,
   return h.breakdown ? SUBMAT_EBREAKDOWN : SUBMAT_OK;
 }
 
+int refine_inverse_impl(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* x_vals,
+                        int32_t n, int64_t nnz, double* xd, int max_iter, double tol, int32_t* iters,
+                        double* residual, hipStream_t s) {
+  DeviceCtx* ctx = nullptr;
+  KrylovPattern* K = nullptr;
+  int rc;
+  if ((rc = get_ctx(&ctx)) || (rc = get_krylov(rowptr, colind, n, nnz, s, ctx, &K))) return rc;
+  const size_t nn = (size_t)n * n;
+  const int RB = reduction_blocks();
+  if ((rc = ensure(K->dense, 3 * nn)) || (rc = ensure(K->small, (size_t)2 + RB))) return rc;
+  if (!ctx->blas && rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
+    ctx->blas = nullptr;
+    return SUBMAT_EHIP;
+  }
+  if (rocblas_set_stream(ctx->blas, s) != rocblas_status_success) return SUBMAT_EHIP;
+  double* Ad = K->dense.p;
+  double* T = Ad + nn;
+  double* U = T + nn;
+  double* fro2 = K->small.p;
+  KrylovScratch ks{fro2 + 2, K->ticket.p};
+  HIP_TRY(hipMemsetAsync(Ad, 0, nn * sizeof(double), s));
+  HIP_TRY(hipMemsetAsync(xd, 0, nn * sizeof(double), s));
+  HIP_TRY(launch_densify(rowptr, colind, a_vals, n, 0, Ad, s));
+  HIP_TRY(launch_densify(rowptr, colind, x_vals, n, 1, xd, s));
+  // Row-major M is column-major M^T: T = A X is T^T = X^T A^T, and
+  // U = 2 X - X T is U^T = 2 X^T - T^T X^T.
+  const double one = 1.0, zero = 0.0, minus_one = -1.0, two = 2.0;
+  double* X = xd;
+  double res = 0.0, res0 = -1.0;
+  int k = 0;
+  bool converged = false, diverged = false;
+  for (;;) {
+    if (rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &one, X, n, Ad, n, &zero, T,
+                      n) != rocblas_status_success)
+      return SUBMAT_EHIP;
+    HIP_TRY(launch_residual_fro2(T, n, ks, fro2, s));
+    double h = 0.0;
+    HIP_TRY(hipMemcpyAsync(&h, fro2, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    res = std::sqrt(h / n);
+    if (res0 < 0.0) res0 = res;
+    if (res <= tol) { converged = true; break; }
+    if (!std::isfinite(res) || res > 1e3 * (res0 > 1.0 ? res0 : 1.0)) { diverged = true; break; }
+    if (k >= max_iter) break;
+    HIP_TRY(hipMemcpyAsync(U, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (rocblas_dgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n, n, n, &minus_one, T, n, X, n, &two,
+                      U, n) != rocblas_status_success)
+      return SUBMAT_EHIP;
+    std::swap(X, U);
+    ++k;
+  }
+  if (X != xd) HIP_TRY(hipMemcpyAsync(xd, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (iters) *iters = k;
+  if (residual) *residual = res;
+  return converged ? SUBMAT_OK : (diverged || k >= max_iter ? SUBMAT_ENOCONV : SUBMAT_OK);
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -918,6 +982,7 @@ const char* submat_strerror(int32_t code) {
     case SUBMAT_ETOOBIG: return "submatrix order exceeds SUBMAT_MAX_ORDER";
     case SUBMAT_ESAVED: return "saved buffer does not match";
     case SUBMAT_EBREAKDOWN: return "CG breakdown (operator not positive definite)";
+    case SUBMAT_ENOCONV: return "refinement did not converge";
     default: return "unknown status code";
   }
 }
@@ -958,6 +1023,17 @@ int submat_residual_norm(const int32_t* rowptr, const int32_t* colind, const dou
   std::lock_guard<std::mutex> lk(g_mu);
   return residual_norm_impl(rowptr, colind, a_vals, x_vals, n, nnz, p, max_iter, tol, norm, iters,
                             (hipStream_t)stream);
+}
+
+int submat_refine_inverse(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* x_vals,
+                          int32_t n, int64_t nnz, double* x_dense, int32_t max_iter, double tol, int32_t* iters,
+                          double* residual, void* stream) {
+  int rc = check_krylov_args(rowptr, colind, n, nnz);
+  if (rc) return rc;
+  if (!a_vals || !x_vals || !x_dense || max_iter < 0 || !(tol >= 0.0) || n > 65536) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  return refine_inverse_impl(rowptr, colind, a_vals, x_vals, n, nnz, x_dense, max_iter, tol, iters, residual,
+                             (hipStream_t)stream);
 }
 
 int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_vals, const double* k_vals, int32_t n,

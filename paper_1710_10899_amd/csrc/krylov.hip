@@ -401,3 +401,52 @@ hipError_t launch_cg_direction(double* p, const double* r, int64_t n, const CgSt
 int reduction_blocks() { return kRedGrid; }
 
 }  // namespace submat
+
+namespace submat {
+
+// ------------------------------------------------------------ refinement
+// Dense row-major n x n image of a CSR value array: column-based
+// (segment j = column j, colbased = 1) or row-based. The target is zeroed
+// first by the caller.
+__global__ __launch_bounds__(kKB) void k_densify(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                                 const double* __restrict__ vals, int n, int colbased,
+                                                 double* __restrict__ D) {
+  const int seg = (int)((blockIdx.x * (int64_t)kKB + threadIdx.x) / kKW);
+  const int lane = threadIdx.x & (kKW - 1);
+  if (seg >= n) return;
+  for (int q = rowptr[seg] + lane; q < rowptr[seg + 1]; q += kKW) {
+    const int64_t r = colbased ? colind[q] : seg, c = colbased ? seg : colind[q];
+    D[r * n + c] = vals[q];
+  }
+}
+
+// out = ||T - I||_F^2 over a dense row-major n x n matrix (deterministic)
+__global__ __launch_bounds__(kKB) void k_residual_fro2(const double* __restrict__ T, int n, double* partials,
+                                                       uint32_t* ticket, double* out) {
+  __shared__ double sh[kKB / kKW];
+  const int64_t nn = (int64_t)n * n;
+  double v = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)kKB + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kKB) {
+    const int64_t i = e / n, j = e - i * n;
+    const double d = T[e] - (i == j ? 1.0 : 0.0);
+    v = fma(d, d, v);
+  }
+  v = block_sum(v, sh);
+  double tot;
+  if (grid_reduce_last(v, partials, ticket, &tot)) *out = tot;
+}
+
+hipError_t launch_densify(const int32_t* rowptr, const int32_t* colind, const double* vals, int n, int colbased,
+                          double* D, hipStream_t s) {
+  const int64_t threads = (int64_t)n * kKW;
+  hipLaunchKernelGGL(k_densify, dim3((unsigned)((threads + kKB - 1) / kKB)), dim3(kKB), 0, s, rowptr, colind, vals, n,
+                     colbased, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_fro2(const double* T, int n, KrylovScratch& k, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_fro2, dim3(kRedGrid), dim3(kKB), 0, s, T, n, k.partials, k.ticket, out);
+  return hipGetLastError();
+}
+
+}  // namespace submat

@@ -57,4 +57,8 @@ hipError_t launch_cg_update(double* x, double* r, const double* p, const double*
                             KrylovScratch& k, hipStream_t s);
 hipError_t launch_cg_direction(double* p, const double* r, int64_t n, const CgState* st, hipStream_t s);
 
+hipError_t launch_densify(const int32_t* rowptr, const int32_t* colind, const double* vals, int n, int colbased,
+                          double* D, hipStream_t s);
+hipError_t launch_residual_fro2(const double* T, int n, KrylovScratch& k, double* out, hipStream_t s);
+
 }  // namespace submat

@@ -171,3 +171,52 @@ def test_cg_edge_cases(gpu_lib):
     neg[diag] = -neg[diag] * 10
     x, info = sm.pcg(rp, ci, neg, ones)
     assert info["breakdown"]
+
+
+# ---------------------------------------------------------------------------
+# Refinement of the inverse (Section 4.5)
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4])
+def test_refine_inverse_matches_oracle(kappa, gpu_lib):
+    """GPU Newton-Schulz from the GPU submatrix inverse against the oracle's
+    from its own: same number of steps, both at the inverse."""
+    import torch
+    import paper_1710_10899_amd as sm
+    csr = G.overlap_matrix(n_atoms=40, nbf=13, rcut=4.14, kappa=kappa, seed=94)
+    check_launch_shapes(csr)
+    banner(f"refine inverse n={csr.n} kappa={kappa:g}")
+    rp, ci, va, x = gpu_root(csr, 1)
+    X, info = sm.refine_inverse(rp, ci, va, x, tol=1e-13)
+    xo, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, 1)
+    Xo, ko_steps, res_o, ok_o = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, xo, tol=1e-13)
+    Ai = np.linalg.inv(csr.dense())
+    print(f"kappa={kappa:g} gpu steps {info['iters']} residual {info['residual']:.2e}; oracle steps {ko_steps} "
+          f"residual {res_o:.2e}", flush=True)
+    assert info["converged"] and ok_o and info["residual"] <= 1e-13
+    assert abs(info["iters"] - ko_steps) <= 1
+    Xg = X.cpu().numpy()
+    assert rel_fro(Xg, Ai) <= 1e-12 * kappa
+    assert rel_fro(Xg, Xo) <= 1e-12 * kappa
+    # two fixed steps: the iterates themselves agree
+    X2, info2 = sm.refine_inverse(rp, ci, va, x, max_iter=2, tol=0.0)
+    Xo2, k2, _, _ = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, xo, tol=0.0, maxit=2)
+    assert info2["iters"] == k2 == 2 and not info2["converged"]
+    assert rel_fro(X2.cpu().numpy(), Xo2) <= 1e-10
+
+
+def test_refine_inverse_edge_cases(gpu_lib):
+    import torch
+    import paper_1710_10899_amd as sm
+    banner("refine inverse edge cases")
+    # exact seed: no step
+    csr = G.block_diagonal_spd((4, 9, 30), kappa=10.0)
+    rp, ci, va, x = gpu_root(csr, 1)
+    X, info = sm.refine_inverse(rp, ci, va, x, tol=1e-13)
+    assert info["converged"] and info["iters"] == 0
+    assert rel_fro(X.cpu().numpy(), np.linalg.inv(csr.dense())) <= 1e-13
+    # divergent seed (spectral radius 2) is reported, kernels end normally
+    csr = G.diagonal_spd(30)
+    rp, ci, va = to_dev(csr)
+    X, info = sm.refine_inverse(rp, ci, va, 3.0 / va, tol=1e-13)
+    assert not info["converged"]

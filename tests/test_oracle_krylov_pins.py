@@ -151,3 +151,43 @@ def test_cg_stops_on_indefinite_operator():
     A.sort_indices()
     x, it, rel = ko.cg(A.indptr, A.indices, A.data, np.r_[np.zeros(5), np.ones(5)])
     assert it == 0 and rel == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Refinement of the inverse (Section 4.5)
+
+
+def test_refinement_squares_the_residual():
+    """One Newton-Schulz step maps I - A X to (I - A X)^2 exactly."""
+    csr = G.overlap_matrix(n_atoms=20, nbf=13, rcut=4.14, kappa=100.0, seed=92)
+    x, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, 1)
+    A = csr.dense()
+    X0 = ko.column_based_matrix(csr.rowptr, csr.colind, x, csr.n).toarray()
+    X1, k, _, _ = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, x, tol=0.0, maxit=1)
+    E0 = np.eye(csr.n) - A @ X0
+    assert k == 1
+    assert np.linalg.norm((np.eye(csr.n) - A @ X1) - E0 @ E0) <= 1e-12 * max(1.0, np.linalg.norm(E0 @ E0))
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4])
+def test_refinement_converges_to_the_inverse(kappa):
+    csr = G.overlap_matrix(n_atoms=24, nbf=13, rcut=4.14, kappa=kappa, seed=93)
+    x, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, 1)
+    X, k, res, ok = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, x, tol=1e-13)
+    Ai = np.linalg.inv(csr.dense())
+    assert ok and res <= 1e-13 and 1 <= k <= 12
+    assert np.linalg.norm(X - Ai) <= 1e-12 * kappa * np.linalg.norm(Ai)
+
+
+def test_refinement_of_exact_seed_takes_no_step():
+    csr = G.block_diagonal_spd((4, 9, 30), kappa=10.0)
+    x, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, 1)
+    _, k, res, ok = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, x, tol=1e-13)
+    assert ok and k == 0 and res <= 1e-13
+
+
+def test_refinement_detects_divergence():
+    """Diagonal A with X = 3 A^{-1}: I - A X = -2 I, spectral radius 2."""
+    csr = G.diagonal_spd(30)
+    X, k, res, ok = ko.refine_inverse(csr.rowptr, csr.colind, csr.vals, 3.0 / csr.vals, tol=1e-13)
+    assert not ok and res > 2.0

@@ -291,3 +291,35 @@ def test_residual_mutants_are_caught(monkeypatch, name, mutant):
 def test_cg_mutants_are_caught(monkeypatch, mutant):
     monkeypatch.setattr(ko, "cg", mutant)
     assert _some_pin_fails(CG_PINS) >= 1
+
+
+_ORIG_REFINE = ko.refine_inverse
+
+
+def _refine_wrong_product_order(rowptr, colind, avals, xvals, tol=1e-14, maxit=20):
+    """X_{k+1} = 2 X - (A X) X instead of 2 X - X (A X)."""
+    n = len(rowptr) - 1
+    A = ko.row_based_matrix(rowptr, colind, avals, n).toarray()
+    X = ko.column_based_matrix(rowptr, colind, xvals, n).toarray()
+    k, res0 = 0, None
+    while True:
+        T = A @ X
+        res = float(np.linalg.norm(T - np.eye(n)) / np.sqrt(n))
+        res0 = res if res0 is None else res0
+        if res <= tol:
+            return X, k, res, True
+        if not np.isfinite(res) or res > 1e3 * max(res0, 1.0) or k >= maxit:
+            return X, k, res, False
+        X = 2.0 * X - T @ X
+        k += 1
+
+
+REFINE_PINS = [
+    lambda: kpins.test_refinement_squares_the_residual(),
+    lambda: kpins.test_refinement_converges_to_the_inverse(1e4),
+]
+
+
+def test_refinement_mutant_is_caught(monkeypatch):
+    monkeypatch.setattr(ko, "refine_inverse", _refine_wrong_product_order)
+    assert _some_pin_fails(REFINE_PINS) >= 1

@@ -121,6 +121,7 @@ struct Plan {
   int small_max = 64;
   std::vector<int32_t> h_m;
   DevBuf<int32_t> d_m, d_c;
+  DevBuf<int32_t> tpos;   // transpose position of every stored entry (the gather's symmetrisation)
   // buckets (columns, largest m first)
   std::vector<int32_t> small_items, large_items;
   DevBuf<int32_t> d_small, d_large;
@@ -186,6 +187,8 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   int maxm = 0;
   for (int j = 0; j < n; ++j) maxm = std::max(maxm, P.h_m[j]);
   if (maxm > SUBMAT_MAX_ORDER) return SUBMAT_ETOOBIG;
+  if ((rc = P.tpos.alloc(nnz))) return rc;
+  HIP_TRY(launch_transpose_positions(rowptr, colind, n, P.tpos.p, stream));
 
   // buckets in longest-processing-time order (largest m first)
   std::vector<int32_t> order(n);
@@ -399,6 +402,7 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
   LargeArgs a{};
   a.rowptr = P.rowptr;
   a.colind = P.colind;
+  a.tpos = P.tpos.p;
   a.vals = c.vals;
   a.vdtype = c.vdtype;
   a.items = P.d_large.p + g_first;

@@ -65,6 +65,7 @@ hipError_t launch_small(const SmallArgs& a, hipStream_t s);
 struct LargeArgs {
   const int32_t* rowptr;
   const int32_t* colind;
+  const int32_t* tpos;    // per stored entry: position of its transpose entry
   const void* vals;
   int vdtype;
   const int32_t* items;   // chunk items -> column id

@@ -48,10 +48,13 @@ __device__ __forceinline__ bool skip_item(const LargeArgs& a, int it) {
 // ---------------------------------------------------------------- gather
 template <class T, class VT>
 __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
-  extern __shared__ int R[];  // max_m ints
+  // LDS: R (max_m ints), then one column buffer of max_m doubles per wave
+  extern __shared__ double gdyn[];
   __shared__ int s_item;
+  int* R = (int*)gdyn;
   const VT* vals = (const VT*)a.vals;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  double* col = gdyn + (a.max_m + 1) / 2 + (size_t)wv * a.max_m;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -62,26 +65,30 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
     const int ld = a.ldm[it];
     T* S = at<T>(a.S, a.off[it]);
     for (int i = tid; i < m; i += kBlock) R[i] = a.colind[a0 + i];
-    const int64_t tot = (int64_t)ld * ld;
-    for (int64_t q = tid; q < tot; q += kBlock) S[q] = T(0);
     __syncthreads();
-    for (int k = wv; k < m; k += kNW) {
+    // Column k of (S + S^T)/2 is built in LDS from row R[k] of A (the
+    // partner A[R[l]][R[k]] of each stored A[R[k]][R[l]] is at its
+    // transpose position) and stored with contiguous writes; the padding
+    // rows and columns of the ld x ld slot are zero.
+    for (int k = wv; k < ld; k += kNW) {
+      T* dst = S + (int64_t)k * ld;
+      if (k >= m) {
+        for (int l = lane; l < ld; l += kWave) dst[l] = T(0);
+        continue;
+      }
+      for (int l = lane; l < m; l += kWave) col[l] = 0.0;
+      __builtin_amdgcn_wave_barrier();
       const int r = R[k];
       const int s0 = a.rowptr[r], s1 = a.rowptr[r + 1];
       for (int q = s0 + lane; q < s1; q += kWave) {
         const int l = find_sorted(R, m, a.colind[q]);
-        if (l >= 0) S[(int64_t)l * ld + k] = (T)vals[q];
+        if (l >= 0) col[l] = 0.5 * ((double)vals[q] + (double)vals[a.tpos[q]]);
       }
+      __builtin_amdgcn_wave_barrier();
+      for (int l = lane; l < ld; l += kWave) dst[l] = l < m ? (T)col[l] : T(0);
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // (S + S^T)/2: wave w owns columns l = w, w+NW, ..., lanes run over k > l
-    for (int l = wv; l < m; l += kNW) {
-      for (int k = l + 1 + lane; k < m; k += kWave) {
-        const T t = T(0.5) * (S[(int64_t)l * ld + k] + S[(int64_t)k * ld + l]);
-        S[(int64_t)l * ld + k] = t;
-        S[(int64_t)k * ld + l] = t;
-      }
-    }
   }
 }
 
@@ -1232,7 +1239,8 @@ static size_t vec_lds(const LargeArgs& a, int nvec, size_t elt) { return (size_t
 
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  const size_t lds = (size_t)a.max_m * sizeof(int);
+  const size_t lds = ((size_t)(a.max_m + 1) / 2 + (size_t)kNW * a.max_m) * sizeof(double);
+  if ((int64_t)lds > a.lds_limit) return hipErrorInvalidValue;
   if (a.fp64) {
     SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_gather_large<double, VT>), dim3(a.grid), dim3(kBlock), lds, s, a));
   } else {

@@ -6,9 +6,9 @@
 //   C[M x N] = alpha * op(A)[M x K] * op(B)[K x N] + beta * C
 //
 // All matrices column-major in global memory. The workgroup (NW waves)
-// walks C in BM x BN tiles, BM = 64, BN = 16 * NW;
-// wave w owns the 32 x 32 block (w % 2, w / 2) of the tile as 2 x 2 MFMA
-// output tiles. Operand tiles of depth BK = 16 are staged through LDS,
+// walks C in BM x BN tiles, BM = 32 * TM, BN = 8 * NW * TN; wave w owns the
+// (16 TM) x (16 TN) block (w % 2, w / 2) of the tile as TM x TN MFMA output
+// tiles (2 x 2 by default; larger blocks read each operand fewer times). Operand tiles of depth BK = 16 are staged through LDS,
 // k-major, so that every lane reads its MFMA operand without bank
 // conflicts.
 //
@@ -58,8 +58,10 @@ template <int W> constexpr int tile_elems_minor() { return W * (kGemmBK + 1); }
 template <int W> constexpr int tile_elems() {
   return tile_elems_major<W>() > tile_elems_minor<W>() ? tile_elems_major<W>() : tile_elems_minor<W>();
 }
-// LDS elements of T needed by wg_gemm with NW waves.
-template <int NW> constexpr int gemm_lds_elems() { return tile_elems<kGemmBM>() + tile_elems<16 * NW>(); }
+// LDS elements of T needed by wg_gemm with NW waves and TM x TN tiles per wave.
+template <int NW, int TM = 2, int TN = 2> constexpr int gemm_lds_elems() {
+  return tile_elems<32 * TM>() + tile_elems<8 * NW * TN>();
+}
 
 // TA: op(A) = A^T (A stored K x M); TB: op(B) = B^T (B stored N x K).
 // LOWER: tiles lying entirely above the diagonal of C are skipped (for
@@ -68,11 +70,12 @@ template <int NW> constexpr int gemm_lds_elems() { return tile_elems<kGemmBM>() 
 // PF: k-tiles fetched ahead into registers while the current one is
 // multiplied (0, 1 or 2; each costs 6-8 registers). Two tiles in flight
 // cover the HBM latency, which exceeds the MFMA time of one 16-deep k-tile.
-template <class T, int NW, bool TA, bool TB, bool LOWER = false, int PF = 1>
+template <class T, int NW, bool TA, bool TB, bool LOWER = false, int PF = 1, int TM = 2, int TN = 2>
 __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, int lda,
                         const T* __restrict__ B, int ldb, T beta, T* __restrict__ C, int ldc, T* smem) {
   static_assert(PF >= 0 && PF <= 2, "prefetch depth 0..2");
-  constexpr int BM = kGemmBM, BK = kGemmBK, BN = 16 * NW, NT = NW * kWave;
+  constexpr int BM = 32 * TM, BK = kGemmBK, BN = 8 * NW * TN, NT = NW * kWave;
+  constexpr int WM = 16 * TM, WN = 16 * TN;  // one wave's block of C
   constexpr int AL = BM * BK / NT, BL = BN * BK / NT;  // tile elements per thread
   constexpr int NS = PF > 1 ? PF : 1;                  // register slots
   typedef typename Mfma<T>::acc_t acc_t;
@@ -103,11 +106,11 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
   for (int i0 = 0; i0 < M; i0 += BM) {
     for (int j0 = 0; j0 < N; j0 += BN) {
       if (LOWER && j0 >= i0 + BM) continue;
-      acc_t acc[2][2];
+      acc_t acc[TM][TN];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+        for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
       T ra[NS][AL], rb[NS][BL];
       auto fetch = [&](int slot, int k0) {
 #pragma unroll
@@ -146,15 +149,15 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
         if (PF > 0 && k0 + PF * BK < K) fetch(slot, k0 + PF * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-          T av[2], bv[2];
+          T av[TM], bv[TN];
 #pragma unroll
-          for (int a = 0; a < 2; ++a) av[a] = a_at(kk + lk, wr * 32 + a * 16 + li);
+          for (int a = 0; a < TM; ++a) av[a] = a_at(kk + lk, wr * WM + a * 16 + li);
 #pragma unroll
-          for (int b = 0; b < 2; ++b) bv[b] = b_at(kk + lk, wc * 32 + b * 16 + li);
+          for (int b = 0; b < TN; ++b) bv[b] = b_at(kk + lk, wc * WN + b * 16 + li);
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < TM; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
         }
       };
       if (PF >= 1) fetch(0, 0);
@@ -169,13 +172,13 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
       }
       // epilogue
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < TM; ++a) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int gj = j0 + wc * 32 + b * 16 + li;
+        for (int b = 0; b < TN; ++b) {
+          const int gj = j0 + wc * WN + b * 16 + li;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int gi = i0 + wr * 32 + a * 16 + Mfma<T>::row(lk, r);
+            const int gi = i0 + wr * WM + a * 16 + Mfma<T>::row(lk, r);
             if (gi < M && gj < N) {
               T* cp = C + (int64_t)gj * ldc + gi;
               *cp = (beta == T(0)) ? alpha * acc[a][b][r] : alpha * acc[a][b][r] + beta * *cp;

@@ -92,6 +92,8 @@ struct LargeArgs {
   double kappa_max;
   double cluster_tol;     // relative eigenvalue gap below which inverse iteration is used
   int lds_limit;          // device limit on LDS bytes per workgroup
+  int panel_rows;         // reduction: rows of the panel kept in LDS (set by its launcher)
+  int panel_off;          // reduction: offset (doubles) of that copy after the row partials
   void* x;                // forward output (value type vdtype)
   const void* gx;         // backward input
   void* ga;               // backward output (accumulated)

@@ -137,9 +137,14 @@ __device__ __forceinline__ double wave_strip_sum(double (&x)[kStrip]) {
 // Column dots of strip [c0, c0 + kStrip) of a panel P (n rows, ncol
 // columns, leading dimension ld): z[c] = P[:, c]^T v, with the lane
 // partials and the reduction of the symv's strips.
+// Rows [0, nl) of the panel are read from its LDS copy L (row-major, stride
+// kPanelLd, the panel's column c at L[row * kPanelLd + c]), the rest from
+// global memory.
+constexpr int kPanelLd = kNB + 1;  // odd stride: the lanes of a column read spread over the banks
 template <class T>
 __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld, int n, int ncol, int c0,
-                                                 const double* __restrict__ v, double* z, int lane, int pl) {
+                                                 const double* __restrict__ v, double* z, int lane, int pl,
+                                                 const double* __restrict__ L, int nl) {
   double cd[kStrip];
   int col[kStrip];
 #pragma unroll
@@ -148,7 +153,15 @@ __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld
     cd[u] = 0.0;
     col[u] = (c < ncol ? c : c0) * ld;
   }
-  for (int r = lane; r - lane < n; r += 2 * kWave) {
+  for (int r = lane; r < nl; r += kWave) {
+    const double vr = v[r];
+#pragma unroll
+    for (int u = 0; u < kStrip; ++u) {
+      const int c = c0 + (u ^ pl);
+      cd[u] = fma(c < ncol ? L[r * kPanelLd + (c < ncol ? c : 0)] : 0.0, vr, cd[u]);
+    }
+  }
+  for (int r = nl + lane; r - lane < n; r += 2 * kWave) {
     const int r2 = r + kWave;
     const bool in = r < n, in2 = r2 < n;
     const uint32_t ra = in ? r : 0, rb = in2 ? r2 : 0;
@@ -176,7 +189,8 @@ __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld
 template <class T>
 __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
                                   double* spart, int max_m, const T* __restrict__ Vp, const T* __restrict__ Wp,
-                                  int npc, double* z1, double* z2) {
+                                  int npc, double* z1, double* z2, const double* __restrict__ Vl,
+                                  const double* __restrict__ Wl, int nl) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int pl = strip_perm(lane);
   double* my = spart + (int64_t)wv * max_m;
@@ -189,7 +203,8 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
     if (s >= nstrip) break;
     if (s < nextra) {
       const bool isw = s < nps;
-      panel_strip_dots(isw ? Wp : Vp, ld, n, npc, (isw ? s : s - nps) * kStrip, v, isw ? z1 : z2, lane, pl);
+      panel_strip_dots(isw ? Wp : Vp, ld, n, npc, (isw ? s : s - nps) * kStrip, v, isw ? z1 : z2, lane, pl,
+                       isw ? Wl : Vl, nl);
       continue;
     }
     const int c0 = (s - nextra) * kStrip;
@@ -257,7 +272,7 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
 // acc - sum_{c<i} (P[c*ld] a[c] + Q[c*ld] b[c]) with eight loads in flight
 // (P, Q: the same row of two column-major panels).
 template <class T>
-__device__ __forceinline__ double panel_correct(const T* __restrict__ P, const T* __restrict__ Q, int ld,
+__device__ __forceinline__ double panel_correct(const T* __restrict__ P, const T* __restrict__ Q, int64_t ld,
                                                 const double* a, const double* b, int i, double acc) {
   double acc1 = 0.0;
   int c = 0;
@@ -303,7 +318,7 @@ static_assert(kRedRows * kRedBlock >= 2048, "row passes cover the largest suppor
 // y -= sum_{c<i} P[c] z1[c] + Q[c] z2[c] and an -= sum_{c<i} P[c] wr[c] +
 // Q[c] vr[c] from one set of loads (P, Q: the same row of V and W).
 template <class T>
-__device__ __forceinline__ void panel_correct2(const T* __restrict__ P, const T* __restrict__ Q, int ld,
+__device__ __forceinline__ void panel_correct2(const T* __restrict__ P, const T* __restrict__ Q, int64_t ld,
                                                const double* z1, const double* z2, const double* wr,
                                                const double* vr, int i, double& y, double& an) {
   double y1 = 0.0, a1 = 0.0;
@@ -349,6 +364,12 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
   double* sy = spart;
   double* sa = spart + a.max_m;
   T* gsm = (T*)spart;
+  // LDS copy of the current panel's V and W on its first pc rows (row k0 + 1
+  // onwards), so that the panel dots and the corrections of most rows do
+  // not go back to global memory
+  const int pc = a.panel_rows;
+  double* Vl = spart + (int64_t)a.panel_off;
+  double* Wl = Vl + (int64_t)pc * kPanelLd;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -400,6 +421,7 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
           const double vq = (q == 0) ? 1.0 : xq * scale;
           sv[q] = vq;
           x[q] = (T)vq;
+          if (i + q < pc) Vl[(i + q) * kPanelLd + i] = (double)(T)vq;
         }
         if (tid == 0) {
           d[k] = (T)dkk;
@@ -412,8 +434,10 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
         // (3) y = A22 v, lower triangle only: every element is read once and
         // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r]; the
         // panel dots z1 = W^T v, z2 = V^T v run as extra strips.
+        const int nl = pc - i > 0 ? (pc - i < n2 ? pc - i : n2) : 0;  // cached rows of this column
         symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m,
-                          S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2);
+                          S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2, Vl + i * kPanelLd,
+                          Wl + i * kPanelLd, nl);
         __syncthreads();
         // each thread sums its rows' partials (fixed order), applies
         // y -= V z1 + W z2 and, from the same loads, the next column's
@@ -428,14 +452,20 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
             double acc = spart[r];
 #pragma unroll
             for (int w = 1; w < kRedNW; ++w) acc += spart[(int64_t)w * a.max_m + r];
+            const bool cached = r < nl;
             if (fuse_next) {
               double nx = (double)S[(int64_t)(k + 1) * ld + (k + 1 + r)];
-              if (i > 0)
-                panel_correct2(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, wk, vk, i, acc,
-                               nx);
+              if (i > 0) {
+                if (cached)
+                  panel_correct2(Vl + (i + r) * kPanelLd, Wl + (i + r) * kPanelLd, 1, z1, z2, wk, vk, i, acc, nx);
+                else
+                  panel_correct2(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, wk, vk, i, acc,
+                                 nx);
+              }
               an[rr] = nx;
             } else if (i > 0) {
-              acc = panel_correct(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, i, acc);
+              acc = cached ? panel_correct(Vl + (i + r) * kPanelLd, Wl + (i + r) * kPanelLd, 1, z1, z2, i, acc)
+                           : panel_correct(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, i, acc);
             }
             sy[r] = acc;
           }
@@ -453,6 +483,7 @@ __global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
           if (r < n2) {
             const double wr = tk * sy[r] - Kc * sv[r];
             Wb[(int64_t)i * ld + (k + 1 + r)] = (T)wr;
+            if (i + r < pc) Wl[(i + r) * kPanelLd + i] = (double)(T)wr;
             if (fuse_next) sa[r] = an[rr] - sv[r] * w0 - wr;
           }
         }
@@ -1249,10 +1280,23 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// static LDS of k_tridiagonalise (block_sum scratch, the next column's
+// coefficients, panel dots) plus a margin
+constexpr size_t kTridiagStaticLds = 2048;
+
 template <class T>
-static void launch_tridiag_t(const LargeArgs& a, hipStream_t s) {
+static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
+  LargeArgs a = a0;
   const size_t part = vec_lds(a, kRedNW, 8), gemm = gemm_lds_elems<kRedNW>() * sizeof(T);
-  const size_t lds = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
+  const size_t base = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
+  // the panel copy takes what is left of the workgroup's LDS (the kernel
+  // runs one workgroup per compute unit), up to the largest order
+  const int64_t left = (int64_t)a.lds_limit - (int64_t)base - (int64_t)kTridiagStaticLds;
+  int rows = left > 0 ? (int)(left / (2 * kPanelLd * sizeof(double))) : 0;
+  if (rows > a.max_m) rows = a.max_m;
+  a.panel_rows = rows;
+  a.panel_off = (int)((part > gemm ? part : gemm) / sizeof(double));
+  const size_t lds = base + (size_t)rows * 2 * kPanelLd * sizeof(double);
   hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kRedBlock), lds, s, a);
 }
 

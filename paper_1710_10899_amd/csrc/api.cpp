@@ -458,7 +458,14 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
   const bool eig = !(c.bwd && c.saved);
   if (eig) {
     next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(a, s));
-    next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(a, s));
+    {
+      // the reduction runs two 4-wave workgroups per compute unit
+      LargeArgs r = a;
+      if (!per_column) r.grid = persistent_grid(ctx, count, std::max(tune_cu, reduction_blocks_per_cu()));
+      next();
+      r.work_ctr = a.work_ctr;
+      HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(r, s));
+    }
     {
       // the eigensolver's workgroups share a compute unit's LDS
       LargeArgs b = a;

@@ -93,9 +93,11 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
 }
 
 // ------------------------------------------------------- symmetric matvec
-// The reduction runs with 8-wave workgroups (measured faster than two 4-wave
-// workgroups per compute unit: the symv's streaming rate per item decides).
-constexpr int kRedNW = 8;
+// The reduction runs with 4-wave workgroups, two per compute unit (two waves
+// per SIMD): while one item waits on a column's serial steps (norm,
+// reflector, barriers), the other streams its trailing matrix.
+constexpr int kRedNW = 4;
+constexpr int kRedPerCU = 2;  // workgroups per compute unit the LDS budget is shared by
 constexpr int kRedBlock = kRedNW * kWave;
 // y = A v for a symmetric n x n matrix given by its lower triangle (column
 // major, leading dimension ld), v and y in LDS, called by the whole
@@ -312,7 +314,7 @@ __device__ __forceinline__ double panel_correct(const T* __restrict__ P, const T
 // A22 -= V W^T + W V^T on MFMA over the tiles that meet the lower triangle;
 // only the lower triangle is ever read.
 // Outputs: d[0..m), e[0..m-1), tau[0..m-2) and v_k in column k of S.
-constexpr int kRedRows = 4;  // rows per thread in the row passes
+constexpr int kRedRows = 8;  // rows per thread in the row passes
 static_assert(kRedRows * kRedBlock >= 2048, "row passes cover the largest supported order");
 
 // y -= sum_{c<i} P[c] z1[c] + Q[c] z2[c] and an -= sum_{c<i} P[c] wr[c] +
@@ -350,7 +352,7 @@ __device__ __forceinline__ void panel_correct2(const T* __restrict__ P, const T*
 }
 
 template <class T>
-__global__ __launch_bounds__(kRedBlock) void k_tridiagonalise(LargeArgs a) {
+__global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   __shared__ double red[kRedNW];
@@ -1280,6 +1282,8 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int reduction_blocks_per_cu() { return kRedPerCU; }
+
 // static LDS of k_tridiagonalise (block_sum scratch, the next column's
 // coefficients, panel dots) plus a margin
 constexpr size_t kTridiagStaticLds = 2048;
@@ -1289,9 +1293,9 @@ static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
   LargeArgs a = a0;
   const size_t part = vec_lds(a, kRedNW, 8), gemm = gemm_lds_elems<kRedNW>() * sizeof(T);
   const size_t base = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
-  // the panel copy takes what is left of the workgroup's LDS (the kernel
-  // runs one workgroup per compute unit), up to the largest order
-  const int64_t left = (int64_t)a.lds_limit - (int64_t)base - (int64_t)kTridiagStaticLds;
+  // the panel copy takes what is left of the workgroup's share of the LDS
+  // (kRedPerCU workgroups per compute unit), up to the largest order
+  const int64_t left = (int64_t)a.lds_limit / kRedPerCU - (int64_t)base - (int64_t)kTridiagStaticLds;
   int rows = left > 0 ? (int)(left / (2 * kPanelLd * sizeof(double))) : 0;
   if (rows > a.max_m) rows = a.max_m;
   a.panel_rows = rows;

@@ -99,6 +99,7 @@ def test_ill_conditioned_workload_adjoint_sampled_entry(gpu_lib):
     rp, ci, va = to_dev(csr)
     ga = sm.invroot_bwd(rp, ci, va, torch.from_numpy(w).cuda(), 2).cpu().numpy()
     st = sm.query_status()
+    print(f"gpu adjoint done, status {st}", flush=True)
     assert np.all(np.isfinite(ga)) and st["unconverged"] == 0
     rows = np.repeat(np.arange(csr.n), csr.row_sizes())
     q = int(np.random.default_rng(G.BASE_SEED + 206).choice(csr.nnz))
@@ -106,6 +107,9 @@ def test_ill_conditioned_workload_adjoint_sampled_entry(gpu_lib):
     ri = csr.colind[csr.rowptr[i]:csr.rowptr[i + 1]]
     rk = csr.colind[csr.rowptr[k]:csr.rowptr[k + 1]]
     cols = np.intersect1d(ri, rk)
-    ref = oracle.adjoint(csr.rowptr, csr.colind, csr.vals, csr.n, 2, w, cols=cols, check=False)
+    ref = np.zeros(csr.nnz)
+    for c0 in range(0, cols.size, 64):  # the oracle in chunks, printing its progress
+        ref += oracle.adjoint(csr.rowptr, csr.colind, csr.vals, csr.n, 2, w, cols=cols[c0:c0 + 64], check=False)
+        print(f"oracle: {min(c0 + 64, cols.size)} of {cols.size} submatrices", flush=True)
     print(f"entry {q} ({i},{k}) over {cols.size} submatrices: gpu {ga[q]:.15e} oracle {ref[q]:.15e}", flush=True)
     assert abs(ga[q] - ref[q]) <= 1e-9 * max(1.0, np.abs(ref).max())

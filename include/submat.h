@@ -35,7 +35,11 @@
  *
  * Plans are cached by (rowptr, colind, n, nnz, device). The caller must not
  * change a pattern's contents while its plan is cached (call
- * submat_release() after changing it). Calls that overlap in time on
+ * submat_release() after changing it). A new plan's workspace is sized from
+ * the free device memory after the device's other cached plans have been
+ * trimmed, least recently used first, to a quarter of the device; if it
+ * still cannot be allocated, the other plans are dropped and the build is
+ * retried. Calls that overlap in time on
  * different streams may share a plan's workspace and must not run
  * concurrently; serialise them or use one stream.
  *

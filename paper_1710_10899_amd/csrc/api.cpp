@@ -114,6 +114,7 @@ struct GraphEntry {
 
 struct Plan {
   int device = 0;
+  uint64_t last_use = 0;  // plan-cache clock at the last call with this pattern
   const int32_t* rowptr = nullptr;
   const int32_t* colind = nullptr;
   int32_t n = 0;
@@ -155,14 +156,63 @@ std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Plan cache bookkeeping: a use clock for least-recently-used eviction and
+// the device bytes a plan's workspace holds.
+uint64_t g_plan_clock = 0;
+
+int64_t plan_bytes(const Plan& P) {
+  return (int64_t)(P.S.n + P.Q.n + P.W.n + P.dv.n + P.ev.n + P.tv.n + P.escr.n) +
+         4 * (int64_t)(P.tpos.n + P.flags.n + P.counters.n);
+}
+
+// Drop cached plans of this device, least recently used first, until the
+// others hold at most `keep` bytes (all of them for keep < 0). Freeing
+// synchronises the device, so no queued work still uses them.
+void evict_plans(int device, int64_t keep) {
+  for (;;) {
+    int64_t held = 0;
+    auto victim = g_plans.end();
+    for (auto p = g_plans.begin(); p != g_plans.end(); ++p) {
+      if (p->second->device != device) continue;
+      held += plan_bytes(*p->second);
+      if (victim == g_plans.end() || p->second->last_use < victim->second->last_use) victim = p;
+    }
+    if (victim == g_plans.end() || (keep >= 0 && held <= keep)) return;
+    g_plans.erase(victim);
+  }
+}
+
+int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, hipStream_t stream,
+                    DeviceCtx* ctx, Plan** out);
+
+// Cached plan for the pattern, built on first use. A new plan's workspace
+// is sized from the free device memory after the other plans of the device
+// have been trimmed (least recently used first) to a quarter of it; if the
+// allocation still fails, every other plan is dropped and the build retried.
 int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, hipStream_t stream,
                DeviceCtx* ctx, Plan** out) {
   PlanKey key{ctx->device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
+    it->second->last_use = ++g_plan_clock;
     *out = it->second.get();
     return SUBMAT_OK;
   }
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  evict_plans(ctx->device, (int64_t)(total_b / 4));
+  int rc = build_plan_once(rowptr, colind, n, nnz, stream, ctx, out);
+  if (rc == SUBMAT_ENOMEM) {
+    (void)hipGetLastError();
+    evict_plans(ctx->device, -1);
+    rc = build_plan_once(rowptr, colind, n, nnz, stream, ctx, out);
+  }
+  return rc;
+}
+
+int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz, hipStream_t stream,
+                    DeviceCtx* ctx, Plan** out) {
+  PlanKey key{ctx->device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
   auto plan = std::make_unique<Plan>();
   Plan& P = *plan;
   P.device = ctx->device;
@@ -281,6 +331,7 @@ int build_plan(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t 
   HIP_TRY(up(P.d_sdoff.p, P.h_sdoff.data(), nl * 8));
   HIP_TRY(hipStreamSynchronize(stream));
   HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+  P.last_use = ++g_plan_clock;
   *out = plan.get();
   g_plans.emplace(key, std::move(plan));
   return SUBMAT_OK;
@@ -455,17 +506,22 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
   a.grid = per_column ? 1 : persistent_grid(ctx, count, tune_cu);
   const int ph = only_flagged ? PH_FALLBACK : -1;
   auto next = [&]() { a.work_ctr = P.counters.p + (ctr++ % P.ncounters); };
+  // Kernels whose registers and LDS leave room for more workgroups per
+  // compute unit than the tuned value get at least that many (measured on
+  // the overlap workloads: the gather, the column and the
+  // reorthogonalisation are latency-bound, and more resident workgroups
+  // hide it); a workgroup that cannot be resident at once starts later and
+  // finds the work counter exhausted.
+  auto with_grid = [&](int min_per_cu) {
+    LargeArgs o = a;
+    if (!per_column) o.grid = persistent_grid(ctx, count, std::max(tune_cu, min_per_cu));
+    return o;
+  };
   const bool eig = !(c.bwd && c.saved);
   if (eig) {
-    next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(a, s));
-    {
-      // the reduction runs two 4-wave workgroups per compute unit
-      LargeArgs r = a;
-      if (!per_column) r.grid = persistent_grid(ctx, count, std::max(tune_cu, reduction_blocks_per_cu()));
-      next();
-      r.work_ctr = a.work_ctr;
-      HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(r, s));
-    }
+    next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(with_grid(8), s));
+    // the reduction runs two 4-wave workgroups per compute unit
+    next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(with_grid(reduction_blocks_per_cu()), s));
     {
       // the eigensolver's workgroups share a compute unit's LDS
       LargeArgs b = a;
@@ -476,12 +532,12 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
       b.work_ctr = a.work_ctr;
       HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_tridiag_eig(b, s));
     }
-    next(); HIP_SEQ(ph < 0 ? PH_ORTH : ph, launch_eig_orth(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_ORTH : ph, launch_eig_orth(with_grid(4), s));
     next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(a, s));
   }
   next();
   if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(a, s));
-  else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(a, s));
+  else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
   return SUBMAT_OK;
 }
 
@@ -846,6 +902,7 @@ int refine_inverse_impl(const int32_t* rowptr, const int32_t* colind, const doub
   }
   if (X != xd) HIP_TRY(hipMemcpyAsync(xd, X, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  (void)K->dense.alloc(0);  // 3 n^2 doubles: not kept between calls
   if (iters) *iters = k;
   if (residual) *residual = res;
   return converged ? SUBMAT_OK : (diverged || k >= max_iter ? SUBMAT_ENOCONV : SUBMAT_OK);

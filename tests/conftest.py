@@ -21,3 +21,17 @@ def gpu_lib():
         pytest.skip("no GPU")
     from paper_1710_10899_amd import _lib
     return _lib.load()
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _release_library_caches(request):
+    """After each GPU test module, drop the library's cached plans and
+    workspaces, so that the modules do not accumulate device memory."""
+    yield
+    marks = getattr(request.module, "pytestmark", [])
+    marks = marks if isinstance(marks, list) else [marks]
+    if not any(getattr(m, "name", "") == "gpu" for m in marks):
+        return
+    lib = sys.modules.get("paper_1710_10899_amd._lib")
+    if lib is not None and getattr(lib, "_lib", None) is not None:
+        lib.submat_release()

@@ -533,10 +533,10 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
       HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_tridiag_eig(b, s));
     }
     next(); HIP_SEQ(ph < 0 ? PH_ORTH : ph, launch_eig_orth(with_grid(4), s));
-    next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(a, s));
+    next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(with_grid(back_blocks_per_cu()), s));
   }
   next();
-  if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(a, s));
+  if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(with_grid(adjoint_blocks_per_cu()), s));
   else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
   return SUBMAT_OK;
 }

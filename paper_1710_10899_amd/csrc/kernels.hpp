@@ -108,6 +108,8 @@ enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
 int reduction_blocks_per_cu();  // workgroups per compute unit the reduction is laid out for
+int back_blocks_per_cu();       // the same for the back-transformation
+int adjoint_blocks_per_cu();    // and for the adjoint
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);
 hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s);
 hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s);

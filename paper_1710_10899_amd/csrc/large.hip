@@ -28,8 +28,16 @@ namespace submat {
 
 constexpr int kBlock = 256;
 constexpr int kNW = kBlock / kWave;
-constexpr int kBigBlock = 512;
-constexpr int kBigNW = kBigBlock / kWave;
+// The back-transformation runs 4-wave workgroups, two per compute unit:
+// one item's serial WY-factor steps overlap the other's products.
+constexpr int kBackBlock = 256;
+constexpr int kBackNW = kBackBlock / kWave;
+constexpr int kBackPerCU = 2;
+// The adjoint likewise (its products prefetch one k-tile ahead, which keeps
+// it within the registers of two waves per SIMD).
+constexpr int kAdjBlock = 256;
+constexpr int kAdjNW = kAdjBlock / kWave;
+constexpr int kAdjPerCU = 2;
 constexpr int kNB = 32;  // panel width of the reduction and of the WY blocks
 
 template <class T> __device__ __forceinline__ T* at(void* base, int64_t off_bytes) {
@@ -1066,7 +1074,7 @@ size_t apply_scratch_elems(int ld) {
 template <class T>
 __device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh, double* Ts) {
   const int tid = threadIdx.x;
-  for (int q = tid; q < kNBh * kNBh; q += kBigBlock) {
+  for (int q = tid; q < kNBh * kNBh; q += kBackBlock) {
     const int c = q / kNBh, r = q - c * kNBh;
     Ts[q] = (r < nh && c < nh) ? (double)Gm[(int64_t)(c0 + c) * kNBq + (c0 + r)] : 0.0;  // Ts[c*kNBh + r]
   }
@@ -1089,7 +1097,7 @@ __device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh,
     }
   }
   __syncthreads();
-  for (int q = tid; q < kNBh * kNBh; q += kBigBlock) {
+  for (int q = tid; q < kNBh * kNBh; q += kBackBlock) {
     const int c = q / kNBh, r = q - c * kNBh;
     if (r < nh && c < nh) Tm[(int64_t)(c0 + c) * kNBq + (c0 + r)] = (T)Ts[q];
   }
@@ -1097,7 +1105,7 @@ __device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh,
 }
 
 template <class T>
-__global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
+__global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_apply_reflectors(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   __shared__ double Ts[kNBh * kNBh];
@@ -1128,8 +1136,8 @@ __global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
       const int nh1 = nbt < kNBh ? nbt : kNBh, nh2 = nbt - nh1;
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
       T* Qs = Q + (k0 + 1);
-      wg_gemm<T, kBigNW, true, false, false, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
-      for (int q = tid; q < kNBq * kNBq; q += kBigBlock) Tm[q] = T(0);
+      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
+      for (int q = tid; q < kNBq * kNBq; q += kBackBlock) Tm[q] = T(0);
       __syncthreads();
       wy_factor_half<T>(Gm, Tm, tau + k0, 0, nh1, Ts);
       if (nh2 > 0) {
@@ -1137,14 +1145,14 @@ __global__ __launch_bounds__(kBigBlock) void k_apply_reflectors(LargeArgs a) {
         // T12 = -T1 (G12 T2): X = G12 T2, then T12 = -T1 X
         const T* G12 = Gm + (int64_t)kNBh * kNBq;                  // rows 0.., columns kNBh..
         const T* T22 = Tm + (int64_t)kNBh * kNBq + kNBh;
-        wg_gemm<T, kBigNW, false, false, false, 1>(nh1, nh2, nh2, T(1), G12, kNBq, T22, kNBq, T(0), Xm, kNBh, gsm);
-        wg_gemm<T, kBigNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
+        wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh2, T(1), G12, kNBq, T22, kNBq, T(0), Xm, kNBh, gsm);
+        wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
                                                    Tm + (int64_t)kNBh * kNBq, kNBq, gsm);
       }
       // VT = V T^T (n2 x nbt), Wm = VT^T Q_sub (nbt x m), Q_sub -= V Wm
-      wg_gemm<T, kBigNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0), VT, ld, gsm);
-      wg_gemm<T, kBigNW, true, false, false, 2>(nbt, m, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
-      wg_gemm<T, kBigNW, false, false, false, 2>(n2, m, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
+      wg_gemm<T, kBackNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0), VT, ld, gsm);
+      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, m, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
+      wg_gemm<T, kBackNW, false, false, false, 1>(n2, m, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
     }
   }
 }
@@ -1187,7 +1195,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
 // D = T1 Q^T (lower tiles; D is symmetric), then every stored pair
 // (R[k], R[l]) at position q receives D[max(k,l)][min(k,l)].
 template <class T, class VT, bool POW>
-__global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
+__global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -1213,14 +1221,14 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
     const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
     const VT* gx = (const VT*)a.gx + a0;
-    for (int i = tid; i < m; i += kBigBlock) {
+    for (int i = tid; i < m; i += kAdjBlock) {
       R[i] = a.colind[a0 + i];
       w[i] = (double)gx[i];
       bv[i] = (double)Q[(int64_t)i * ld + c];
       alv[i] = spec_node((double)lam[i], a.fn);
     }
     __syncthreads();
-    for (int pc = wv; pc < m; pc += kBigNW) {
+    for (int pc = wv; pc < m; pc += kAdjNW) {
       double part = 0.0;
       for (int r = lane; r < m; r += kWave) part = fma((double)Q[(int64_t)pc * ld + r], w[r], part);
       part = wave_sum(part);
@@ -1228,10 +1236,10 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
     }
     __syncthreads();
     if (POW) {  // lambda^alpha per eigenvalue, into w (no longer needed)
-      for (int i = tid; i < m; i += kBigBlock) w[i] = pow(alv[i], a.fn.alpha);
+      for (int i = tid; i < m; i += kAdjBlock) w[i] = pow(alv[i], a.fn.alpha);
       __syncthreads();
     }
-    for (int l = wv; l < m; l += kBigNW) {
+    for (int l = wv; l < m; l += kAdjNW) {
       const double pwl = POW ? w[l] : 0.0;
       for (int pr = lane; pr < m; pr += kWave) {
         const double g = spec_divdiff<POW>(alv[pr], alv[l], pwl, a.fn);
@@ -1239,10 +1247,10 @@ __global__ __launch_bounds__(kBigBlock) void k_adjoint(LargeArgs a) {
       }
     }
     __syncthreads();
-    wg_gemm<T, kBigNW, false, false, false, 2>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
-    wg_gemm<T, kBigNW, false, true, true, 2>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
+    wg_gemm<T, kAdjNW, false, false, false, 1>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
+    wg_gemm<T, kAdjNW, false, true, true, 1>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
     VT* ga = (VT*)a.ga;
-    for (int k = wv; k < m; k += kBigNW) {
+    for (int k = wv; k < m; k += kAdjNW) {
       const int r = R[k];
       const int s0 = a.rowptr[r], s1 = a.rowptr[r + 1];
       for (int q = s0 + lane; q < s1; q += kWave) {
@@ -1283,6 +1291,8 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
 }
 
 int reduction_blocks_per_cu() { return kRedPerCU; }
+int back_blocks_per_cu() { return kBackPerCU; }
+int adjoint_blocks_per_cu() { return kAdjPerCU; }
 
 // static LDS of k_tridiagonalise (block_sum scratch, the next column's
 // coefficients, panel dots) plus a margin
@@ -1336,9 +1346,9 @@ hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s) {
 hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.fp64)
-    hipLaunchKernelGGL(k_apply_reflectors<double>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 8, s, a);
+    hipLaunchKernelGGL(k_apply_reflectors<double>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 8, s, a);
   else
-    hipLaunchKernelGGL(k_apply_reflectors<float>, dim3(a.grid), dim3(kBigBlock), gemm_lds_elems<kBigNW>() * 4, s, a);
+    hipLaunchKernelGGL(k_apply_reflectors<float>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 4, s, a);
   return hipGetLastError();
 }
 
@@ -1355,7 +1365,7 @@ hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s) {
 
 template <class T, bool POW>
 static void dispatch_adjoint(const LargeArgs& a, size_t lds, hipStream_t s) {
-  SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<T, VT, POW>), dim3(a.grid), dim3(kBigBlock), lds, s, a));
+  SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<T, VT, POW>), dim3(a.grid), dim3(kAdjBlock), lds, s, a));
 }
 
 hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s) {
@@ -1363,10 +1373,10 @@ hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s) {
   const size_t base = ((size_t)(a.max_m + 1) / 2 + 1) * 8 + vec_lds(a, 4, 8);
   const bool pw = a.fn.kind == FN_POWER;
   if (a.fp64) {
-    const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(double);
+    const size_t lds = base + gemm_lds_elems<kAdjNW>() * sizeof(double);
     pw ? dispatch_adjoint<double, true>(a, lds, s) : dispatch_adjoint<double, false>(a, lds, s);
   } else {
-    const size_t lds = base + gemm_lds_elems<kBigNW>() * sizeof(float);
+    const size_t lds = base + gemm_lds_elems<kAdjNW>() * sizeof(float);
     pw ? dispatch_adjoint<float, true>(a, lds, s) : dispatch_adjoint<float, false>(a, lds, s);
   }
   return hipGetLastError();

@@ -38,7 +38,7 @@ constexpr int kBackPerCU = 2;
 constexpr int kAdjBlock = 256;
 constexpr int kAdjNW = kAdjBlock / kWave;
 constexpr int kAdjPerCU = 2;
-constexpr int kNB = 32;  // panel width of the reduction and of the WY blocks
+constexpr int kNB = 16;  // panel width of the reduction (16 measured best of 8..48 at orders ~400)
 
 template <class T> __device__ __forceinline__ T* at(void* base, int64_t off_bytes) {
   return (T*)((char*)base + off_bytes);

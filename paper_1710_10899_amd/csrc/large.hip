@@ -9,7 +9,7 @@
 //               the eigenvectors, local reorthogonalisation (Z into the Q
 //               slab)
 //   back        Q = Q1 Z: the reflectors applied to Z in compact-WY blocks
-//               of 64, products on MFMA
+//               of 128 (two 64-column factors merged), products on MFMA
 //   column      x = Q (f(lambda) o Q[c,:]^T) into X's value segment
 //               (Sections 3.3-3.4)
 //   adjoint     D = Q sym(G o (a b^T)) Q^T on MFMA, scattered into dA's

@@ -81,14 +81,21 @@ def phase_work(m, phase):
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources; HBM counter figures taken for another
-    version of the kernels are not reported."""
+    """sha256 over the HIP library's sources with comments and blank space
+    removed: the counters in profiles/traffic.json stay valid across edits
+    that cannot change a kernel."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    csrc = os.path.join(ROOT, "paper_1710_10899_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+            text = open(os.path.join(csrc, f), encoding="utf-8").read()
+            text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", " ", text)
+            text = " ".join(text.split())
+            h.update(f.encode())
+            h.update(text.encode())
     return h.hexdigest()
 
 
@@ -145,7 +152,7 @@ def summarise_profile(d: str, command: str) -> None:
              "first, output directory then passed to `python bench.py --summarise-profile DIR`):", "", "```",
              command, "```", "",
              f"Counter calibration (1 GiB device copy): FETCH_SIZE x{ctr['fetch'][1]:.3f}, "
-             f"WRITE_SIZE x{ctr['write'][1]:.3f}.", f"Kernel sources sha256: `{sha}`", "",
+             f"WRITE_SIZE x{ctr['write'][1]:.3f}.", f"Kernel sources sha256 (comments and blank space removed): `{sha}`", "",
              "| kernel | phase | calls | avg ms | % time | HBM read GB/launch | HBM write GB/launch | GB/s |",
              "|---|---|---|---|---|---|---|---|"]
     for name, (calls, ms, pct) in sorted(stats.items(), key=lambda kv: -kv[1][2]):

@@ -591,6 +591,22 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
   return cnt;
 }
 
+// The same count over a whole unsplit T (rows 0..m, m the same in every
+// lane): uniform bounds give scalar loop control and constant LDS offsets.
+// After the guard |q| >= pivmin > 0, so q < 0 is its sign bit.
+__device__ __forceinline__ int sturm_count_all(const double* d, const double* e2, int m, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = (int)((uint32_t)__double2hiint(q) >> 31);
+#pragma unroll 4
+  for (int i = 1; i < m; ++i) {
+    q = fma(-e2[i - 1], recip(q), d[i] - x);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (int)((uint32_t)__double2hiint(q) >> 31);
+  }
+  return cnt;
+}
+
 __device__ __forceinline__ double guard_pivot(double D, double tol) {
   return fabs(D) < tol ? (D < 0.0 ? -tol : tol) : D;
 }
@@ -800,7 +816,7 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
     // factor kEigBlock + 1 before the bisection
     const bool one_block = be[0] == m;
     const double hstep = (ghi - glo) / (kEigBlock + 1);
-    if (one_block) msc[tid] = sturm_count(d, e2, 0, m, glo + (tid + 1) * hstep, pivmin);
+    if (one_block) msc[tid] = sturm_count_all(d, e2, m, glo + (tid + 1) * hstep, pivmin);
     __syncthreads();
     for (int jj = tid; jj < m; jj += kEigBlock) {
       const int s = bs[jj], t = be[jj], k = jj - s;
@@ -820,7 +836,8 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
       for (int iter = 0; iter < 256; ++iter) {
         const double mid = 0.5 * (lo + hi);
         if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;
-        if (sturm_count(d, e2, s, t, mid, pivmin) > k) hi = mid;
+        const int cnt = one_block ? sturm_count_all(d, e2, m, mid, pivmin) : sturm_count(d, e2, s, t, mid, pivmin);
+        if (cnt > k) hi = mid;
         else lo = mid;
       }
       lam[jj] = 0.5 * (lo + hi);

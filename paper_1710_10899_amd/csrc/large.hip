@@ -4,8 +4,8 @@
 //   tridiag     blocked Householder reduction S = Q1 T Q1^T (lower form): per
 //               panel of NB columns a lower-triangle symv per column, and one
 //               rank-2*NB trailing update on MFMA
-//   eig         T = Z diag(lambda) Z^T in FP64: bisection for the
-//               eigenvalues, twisted factorisation / inverse iteration for
+//   eig         T = Z diag(lambda) Z^T in FP64: Sturm-count bisection
+//               with Newton steps for the eigenvalues, twisted factorisation / inverse iteration for
 //               the eigenvectors, local reorthogonalisation (Z into the Q
 //               slab)
 //   back        Q = Q1 Z: the reflectors applied to Z in compact-WY blocks
@@ -530,12 +530,15 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
 
 // --------------------------------------------- tridiagonal eigensolver
 // Eigen-decomposition of T = tridiag(e, d, e) in FP64 (Section 3.2 leaves
-// the dense eigensolver open; this is bisection plus inverse iteration):
+// the dense eigensolver open; this is Sturm-count bisection with Newton
+// steps, twisted factorisations and inverse iteration):
 //  * off-diagonals below eps * sqrt(|d_i d_i+1|) are set to zero, which
 //    splits T into unreduced blocks; eigenvalue index j belongs to the block
 //    holding row j;
-//  * eigenvalue j: bisection on the Sturm count of its block (one lane per
-//    eigenvalue), from Gershgorin bounds down to a few ulps;
+//  * eigenvalue j: a bracket from Sturm counts of its block (one lane per
+//    eigenvalue), from Gershgorin bounds down to a few ulps; on an unsplit
+//    T, once the bracket holds eigenvalue j alone, Newton steps on
+//    log det(T - xI) choose the trial points;
 //  * eigenvector of an eigenvalue whose neighbours in its block are further
 //    than ctol * ||T|| away: twisted factorisation T - lambda I =
 //    N_r D_r N_r^T with the twist r minimising |gamma_r|, then
@@ -604,6 +607,31 @@ __device__ __forceinline__ int sturm_count_all(const double* d, const double* e2
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (int)((uint32_t)__double2hiint(q) >> 31);
   }
+  return cnt;
+}
+
+// The count of sturm_count_all together with the logarithmic derivative
+// sd = sum_i q_i'/q_i = d/dx log det(T - xI) = -sum_l 1/(lambda_l - x),
+// from q_i' = -1 + e_{i-1}^2 q_{i-1}' / q_{i-1}^2 (a Newton step for an
+// eigenvalue is -1/sd). The pivots are those of sturm_count_all. Guarded
+// pivots or overflow make sd infinite or NaN, which the caller rejects.
+__device__ __forceinline__ int sturm_newton_all(const double* d, const double* e2, int m, double x, double pivmin,
+                                                double& sd) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = (int)((uint32_t)__double2hiint(q) >> 31);
+  double qp = -1.0, s = 0.0;
+#pragma unroll 4
+  for (int i = 1; i < m; ++i) {
+    const double r = recip(q);
+    s = fma(qp, r, s);
+    const double t = e2[i - 1] * r;
+    qp = fma(t * r, qp, -1.0);
+    q = fma(-e2[i - 1], r, d[i] - x);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (int)((uint32_t)__double2hiint(q) >> 31);
+  }
+  sd = fma(qp, recip(q), s);
   return cnt;
 }
 
@@ -832,13 +860,65 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
         // points 0..a2-1 have count <= k, point a2 (if any) has count > k
         lo = a2 > 0 ? glo + a2 * hstep : glo;
         hi = a2 < kEigBlock ? glo + (a2 + 1) * hstep : ghi;
-      }
-      for (int iter = 0; iter < 256; ++iter) {
-        const double mid = 0.5 * (lo + hi);
-        if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;
-        const int cnt = one_block ? sturm_count_all(d, e2, m, mid, pivmin) : sturm_count(d, e2, s, t, mid, pivmin);
-        if (cnt > k) hi = mid;
-        else lo = mid;
+        int clo = a2 > 0 ? msc[a2 - 1] : 0, chi = a2 < kEigBlock ? msc[a2] : m;
+        // Sturm-safeguarded Newton: the bracket [lo, hi] (counts clo <= k <
+        // chi) is kept exactly as in bisection and the loop ends on the same
+        // width test; only the next trial point differs. While the bracket
+        // holds more than eigenvalue k, it is the midpoint. Once it holds k
+        // alone, it is the Newton point x - 1/sd if that lies inside and the
+        // Newton steps at least halve every two iterations. Newton from one
+        // side never closes the far end, so when the step is within the
+        // tolerance, the trial point goes across the eigenvalue towards the
+        // open end by (|step| + g) 2^j, j counting such probes.
+        double x = 0.5 * (lo + hi), w1 = INFINITY, w2 = INFINITY;
+        int npr = 0;
+        for (int iter = 0; iter < 256; ++iter) {
+          if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(x > lo && x < hi)) break;
+          double sd;
+          const int cnt = sturm_newton_all(d, e2, m, x, pivmin, sd);
+          const bool up = cnt > k;
+          if (up) {
+            hi = x;
+            chi = cnt;
+          } else {
+            lo = x;
+            clo = cnt;
+          }
+          const double g = 2.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + 0.5 * atol;
+          const double step = -1.0 / sd;
+          const double st = fabs(step);
+          const bool iso = chi - clo == 1;
+          const double xb = 0.5 * (lo + hi);
+          double xn = xb, wn = fabs(xb - x);
+          if (iso && !(st > 2.0 * g)) {
+            const double pr = x + (up ? -1.0 : 1.0) * (st + g) * ldexp(1.0, npr);
+            if (pr > lo && pr < hi) {
+              xn = pr;
+              wn = w1;
+              ++npr;
+            } else {
+              npr = 0;
+            }
+          } else {
+            npr = 0;
+            const double xt = x + step;
+            if (iso && xt > lo && xt < hi && !(st > 0.5 * w2)) {
+              xn = xt;
+              wn = st;
+            }
+          }
+          w2 = w1;
+          w1 = wn;
+          x = xn;
+        }
+      } else {
+        for (int iter = 0; iter < 256; ++iter) {
+          const double mid = 0.5 * (lo + hi);
+          if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;
+          const int cnt = sturm_count(d, e2, s, t, mid, pivmin);
+          if (cnt > k) hi = mid;
+          else lo = mid;
+        }
       }
       lam[jj] = 0.5 * (lo + hi);
     }

@@ -951,14 +951,17 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
       e2[jj] = wp ? 1.0 : sc;  // cluster members are normalised by their leader
     }
     __syncthreads();
-    // normalise; zero outside the vector's block
+    // Column jj of Z still has to be scaled by e2[jj]; the scale goes to row
+    // 0 of the U region (dead from here on) and the reorthogonalisation
+    // applies it where it reads the column. On a split T the rows outside a
+    // vector's block are zeroed here.
     for (int jj = tid; jj < m; jj += kEigBlock) {
-      const int s = bs[jj], t = be[jj];
-      const double sc = e2[jj];
-      for (int i = 0; i < m; ++i) {
-        double* zp = Z + (int64_t)i * ld + jj;
-        *zp = (i >= s && i < t) ? *zp * sc : 0.0;
+      if (!one_block) {
+        const int s = bs[jj], t = be[jj];
+        for (int i = 0; i < s; ++i) Z[(int64_t)i * ld + jj] = 0.0;
+        for (int i = t; i < m; ++i) Z[(int64_t)i * ld + jj] = 0.0;
       }
+      U[jj] = e2[jj];
     }
     // eigenvalues, spectrum checks and flags
     double lmin = INFINITY, lmax = -INFINITY;
@@ -1025,6 +1028,7 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
   __shared__ double Cs[kOrthB * kOrthB], Gs[kOrthB * kOrthB], Rs[kOrthB * kOrthB], Ri[kOrthB * kOrthB],
       Ds[kOrthB * kOrthB];
   __shared__ double tile[kOrthB * (kWave + 1)];
+  __shared__ double bsc[kOrthB];  // column scales of the current block
   typedef Mfma<double>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int li = lane & 15, lk = lane >> 4;
@@ -1038,18 +1042,23 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
     const int ld = a.ldm[it];
     T* Qz = at<T>(a.Q, a.qoff[it]);  // Z, column-major, for the back-transformation
     double* Z = at<double>(a.escr, a.eoff[it]);
+    // 1/||z|| of each column as left by the eigensolver (row 0 of the U
+    // region); a block B is scaled as it is read, P is already final
+    const double* zsc = Z + (int64_t)ld * ld;
     if (tid == 0) s_bad = 0;
     for (int j0 = 0; j0 < m; j0 += kOrthB) {
       const int nb = (m - j0) < kOrthB ? (m - j0) : kOrthB;
       double* B = Z + j0;
       const double* P = Z + (j0 - kOrthB);  // used only when j0 > 0
       const bool hasP = j0 > 0;
+      if (tid < kOrthB) bsc[tid] = tid < nb ? zsc[j0 + tid] : 0.0;
+      const double lsc = li < nb ? zsc[j0 + li] : 0.0;
       // pass 1: wave w takes rows 4w.., 4(w+NW).. (four rows per MFMA step)
       acc_t cacc = acc_t{0, 0, 0, 0}, hacc = acc_t{0, 0, 0, 0};
       for (int i0 = 4 * wv; i0 < m; i0 += 4 * kEigNW) {
         const int i = i0 + lk;
         const bool ok = i < m && li < nb;
-        const double bv = ok ? B[(int64_t)i * ld + li] : 0.0;
+        const double bv = ok ? B[(int64_t)i * ld + li] * lsc : 0.0;
         const double pv = (hasP && i < m) ? P[(int64_t)i * ld + li] : 0.0;
         hacc = Mfma<double>::step(bv, bv, hacc);
         cacc = Mfma<double>::step(pv, bv, cacc);
@@ -1102,6 +1111,9 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
         for (int q = 0; q < kOrthB; ++q) dv = fma(Cs[k * kOrthB + q], Ri[q * kOrthB + l], dv);
         Ds[tid] = dv;
       }
+      __syncthreads();
+      // pass 2 reads B unscaled: (B diag(bsc)) Rinv = B (diag(bsc) Rinv)
+      Ri[tid] *= bsc[k];
       __syncthreads();
       // pass 2, 64 rows at a time: thread (row, column); the 16 threads of
       // a row sit in one wave and read the whole row before any of them

@@ -252,6 +252,23 @@ def test_repeated_eigenvalues(gpu_lib):
         assert err <= TOL64 and st["unconverged"] == 0
 
 
+def test_near_degenerate_eigenvalues_unsplit(gpu_lib):
+    """Distinct eigenvalues in groups of four at relative gaps 1e-4, 1e-8 and
+    1e-12 in one dense submatrix of order 160: T does not split, so every
+    eigenvalue is found by the count-safeguarded search, which has to isolate
+    members of a group before its Newton steps apply."""
+    base = np.linspace(1.0, 9.0, 40)
+    eigs = np.concatenate([base, base * (1 + 1e-4), base * (1 + 1e-8), base * (1 + 1e-12)])
+    csr = G.dense_with_spectrum(eigs, seed=G.BASE_SEED + 19)
+    banner("near-degenerate eigenvalues, dense n=160")
+    for p in (1, 2):
+        x, st = gpu_forward(csr, p)
+        ref, _ = oracle_forward(csr, p)
+        err = rel_fro(x, ref)
+        print(f"p={p} rel_err={err:.3e} status={st}", flush=True)
+        assert err <= TOL64 and st["unconverged"] == 0
+
+
 @pytest.mark.parametrize("ctol", [0.0, 1e-2, 0.5])
 def test_cluster_tolerance_paths(ctol, gpu_lib):
     """Twisted factorisation only (0), many clusters (1e-2), every eigenvalue

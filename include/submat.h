@@ -34,14 +34,22 @@
  * device, one device-to-host copy) and allocates the library's workspace.
  *
  * Plans are cached by (rowptr, colind, n, nnz, device). The caller must not
- * change a pattern's contents while its plan is cached (call
- * submat_release() after changing it). A new plan's workspace is sized from
- * the free device memory after the device's other cached plans have been
- * trimmed, least recently used first, to a quarter of the device; if it
- * still cannot be allocated, the other plans are dropped and the build is
- * retried. Calls that overlap in time on
- * different streams may share a plan's workspace and must not run
- * concurrently; serialise them or use one stream.
+ * change a pattern's contents while its plan is cached, nor free the index
+ * arrays and hand their addresses to another pattern of the same n and nnz:
+ * call submat_release_pattern() (or submat_release()) first. A column whose
+ * order no longer fits the cached plan is not computed: its output segment
+ * is NaN and it is counted (submat_query_counters slot 4); no memory
+ * outside the plan's slots is touched.
+ *
+ * Workspaces: each stream gets its own workspace (slabs, per-item flags,
+ * work counters, captured graphs) and its own status counters, allocated at
+ * its first call on a plan; calls on different streams may run concurrently.
+ * A plan keeps at most 4 stream workspaces (the least recently used is
+ * dropped). The workspace is sized from the free device memory when the
+ * plan is built, after the device's other cached plans have been trimmed,
+ * least recently used first, to a quarter of the device; if a workspace
+ * cannot be allocated, the other plans (then this plan's other workspaces)
+ * are dropped and the allocation retried, else SUBMAT_ENOMEM.
  *
  * Errors: every int-returning call returns SUBMAT_OK (0) or a negative code;
  * submat_strerror() names it. Invalid input is reported synchronously and
@@ -105,6 +113,20 @@ extern "C" {
                                     written by the package's autotune module), 0 for the
                                     built-in table; get returns 1 when a file is in use.
                                     The table is first read at the first call. */
+#define SUBMAT_OPT_DETERMINISTIC 7 /* 1: the adjoint is assembled without atomic adds: each
+                                    phase (the one-wavefront launch, each chunk of the
+                                    large-order path) leaves every D_j in memory, then every
+                                    stored entry adds the terms of the columns that share it
+                                    in ascending column order, so grad_a is bit-identical
+                                    from run to run and exactly symmetric (one extra pass
+                                    over the pattern per phase). 0 (default): atomic adds,
+                                    equal up to rounding order. */
+#define SUBMAT_OPT_PLAIN_STRIDE 8 /* measurement aid for SUBMAT_PREC_F64_PLAIN: the per-column
+                                    path computes only every k-th column of each size bucket
+                                    (buckets ordered by decreasing order, so the sample spans
+                                    the order distribution) and leaves the other columns'
+                                    outputs unwritten; k >= 1, default 1 (every column).
+                                    No other precision looks at it. */
 
 /* spectral function f applied to every submatrix, and the meaning of `param` */
 #define SUBMAT_FN_INV_ROOT 0  /* f(lambda) = lambda^(-1/p), param = p, integer >= 1 (Sections 3-4) */
@@ -141,7 +163,11 @@ int submat_matfun_fwd(const int32_t* rowptr, const int32_t* colind, const void* 
  * G is evaluated without cancellation: through alpha = lambda^(1/p) for the
  * roots, through expm1/log1p of the eigenvalue ratio for a real power.
  *   saved   NULL (recompute), or the buffer filled by a forward call with the
- *           same pattern, vals, dtype and precision.
+ *           same pattern, vals, dtype and precision. The library records which
+ *           pattern, dtype and precision each saved buffer was last filled for;
+ *           a buffer not recorded for this call's is rejected synchronously
+ *           with SUBMAT_ESAVED and nothing is written. (It cannot tell whether
+ *           vals changed in between: that remains the caller's contract.)
  */
 int submat_matfun_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals,
                       int32_t n, int64_t nnz, int32_t fn, double param, int32_t dtype,
@@ -164,7 +190,7 @@ int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t
 
 /*
  * Synchronises `stream` and reports the device counters of the last completed
- * fwd/bwd call on the current device: submatrices with an eigenvalue <= 0,
+ * fwd/bwd call on that stream (current device): submatrices with an eigenvalue <= 0,
  * submatrices redone in FP64 by the mixed-precision path, and submatrices whose
  * eigensolver did not converge. Any pointer may be NULL.
  */
@@ -173,11 +199,12 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
 
 /*
  * Synchronises `stream` and copies the first n (n <= 8) device counters of the
- * last completed call on the current device: [0] non-positive submatrices,
- * [1] FP64 redos, [2] unconverged, [3] eigenvectors of the tridiagonal
- * eigensolver (large-order path) computed by inverse iteration because their
- * eigenvalue lies in a cluster. Returns SUBMAT_EINVAL for n outside 1..8 or
- * out NULL.
+ * last completed call on that stream (current device): [0] non-positive
+ * submatrices, [1] FP64 redos, [2] unconverged, [3] eigenvectors of the
+ * tridiagonal eigensolver (large-order path) computed by inverse iteration
+ * because their eigenvalue lies in a cluster, [4] columns not computed because
+ * their order does not fit the cached plan (the pattern changed under it).
+ * Returns SUBMAT_EINVAL for n outside 1..8 or out NULL.
  */
 int submat_query_counters(void* stream, int64_t* out, int32_t n);
 
@@ -259,6 +286,12 @@ int submat_refine_inverse(const int32_t* rowptr, const int32_t* colind, const do
 
 /* Drop every cached plan, graph and workspace (synchronises the device). */
 void submat_release(void);
+
+/* Drop the cached plan, workspaces, graphs and Krylov data of one pattern
+   (key rowptr, colind, n, nnz on the current device; synchronises the device
+   when something is freed). Call it before the pattern's index arrays are
+   freed or changed. Unknown keys are not an error. SUBMAT_EINVAL for NULL. */
+int submat_release_pattern(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz);
 
 /* ABI version: 100*major + minor. */
 int32_t submat_version(void);

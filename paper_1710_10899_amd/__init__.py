@@ -15,7 +15,8 @@ from ._lib import (  # noqa: F401
 )
 
 __all__ = ["invroot", "invroot_fwd", "invroot_bwd", "invroot_csr", "matfun", "matfun_fwd", "matfun_bwd",
-           "matfun_csr", "spmv", "residual_norm", "pcg", "refine_inverse", "saved_bytes", "query_status", "time_phases", "MatFun"]
+           "matfun_csr", "spmv", "residual_norm", "pcg", "refine_inverse", "saved_bytes", "query_status", "time_phases", "MatFun",
+           "release_pattern"]
 
 
 def __getattr__(name):

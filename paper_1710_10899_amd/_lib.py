@@ -41,6 +41,8 @@ SUBMAT_OPT_SMALL_MAX = 3
 SUBMAT_OPT_WS_BYTES = 4
 SUBMAT_OPT_CLUSTER_TOL = 5
 SUBMAT_OPT_TUNE_FILE = 6
+SUBMAT_OPT_DETERMINISTIC = 7
+SUBMAT_OPT_PLAIN_STRIDE = 8
 SUBMAT_NUM_PHASES = 10
 
 PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "tridiagonal-eig", "reorthogonalise",
@@ -63,6 +65,7 @@ SIGNATURES = {
     "submat_get_option": (ctypes.c_double, [_I32]),
     "submat_strerror": (ctypes.c_char_p, [_I32]),
     "submat_release": (None, []),
+    "submat_release_pattern": (ctypes.c_int, [_P, _P, _I32, _I64]),
     "submat_version": (_I32, []),
     "submat_spmv": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _P, _P, _P]),
     "submat_residual_norm": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I64, _I32, _I32, _D, ctypes.POINTER(_D),
@@ -170,6 +173,10 @@ def submat_strerror(code: int) -> str:
 
 def submat_release() -> None:
     load().submat_release()
+
+
+def submat_release_pattern(rowptr, colind, n, nnz) -> None:
+    _check(load().submat_release_pattern(rowptr, colind, n, nnz), "submat_release_pattern")
 
 
 def submat_version() -> int:

@@ -13,6 +13,8 @@ roots, the exponent alpha for a real power):
 """
 from __future__ import annotations
 
+import weakref
+
 import torch
 
 from . import _lib
@@ -248,6 +250,44 @@ def invroot(rowptr, colind, vals, p: int = 2, precision="f64", keep_eigvecs: boo
                         bool(keep_eigvecs))
 
 
+def release_pattern(rowptr: torch.Tensor, colind: torch.Tensor) -> None:
+    """Drops the library's cached plan for this pattern (call it before the
+    index tensors are freed or changed when another pattern of the same n
+    and nnz may take their addresses)."""
+    _lib.submat_release_pattern(rowptr.data_ptr(), colind.data_ptr(), rowptr.numel() - 1, colind.numel())
+
+
+# int32 index tensors of the sparse CSR tensors passed to matfun_csr, by id()
+# of the sparse tensor: (weak reference to it, rowptr, colind). A finalizer
+# drops the entry and the library's plan for those addresses when the sparse
+# tensor goes away, so that a later pattern that reuses the addresses never
+# meets a stale plan.
+_CSR_INDEX = {}
+
+
+def _forget_csr(key, rp_ptr, ci_ptr, n, nnz):
+    _CSR_INDEX.pop(key, None)
+    if _lib._lib is not None:
+        _lib.submat_release_pattern(rp_ptr, ci_ptr, n, nnz)
+
+
+def _csr_index32(a: torch.Tensor):
+    """(rowptr, colind) of a sparse CSR tensor as int32 device tensors whose
+    addresses stay fixed while `a` lives, and whose plan is released when it
+    dies."""
+    key = id(a)
+    hit = _CSR_INDEX.get(key)
+    if hit is not None and hit[0]() is a:
+        return hit[1], hit[2]
+    crow, col = a.crow_indices(), a.col_indices()
+    rowptr = crow if crow.dtype == torch.int32 and crow.is_contiguous() else crow.to(torch.int32).contiguous()
+    colind = col if col.dtype == torch.int32 and col.is_contiguous() else col.to(torch.int32).contiguous()
+    _CSR_INDEX[key] = (weakref.ref(a), rowptr, colind)
+    weakref.finalize(a, _forget_csr, key, rowptr.data_ptr(), colind.data_ptr(), rowptr.numel() - 1,
+                     colind.numel())
+    return rowptr, colind
+
+
 def invroot_csr(a: torch.Tensor, p: int = 2, precision="f64") -> torch.Tensor:
     """X for a torch sparse CSR matrix A, sharing A's index tensors (the
     pattern is reused, Section 3.4)."""
@@ -258,7 +298,6 @@ def matfun_csr(a: torch.Tensor, fn="inv_root", param: float = 2, precision="f64"
     """f(A) for a torch sparse CSR matrix A, on A's pattern and index tensors."""
     if a.layout != torch.sparse_csr:
         raise ValueError("expected a sparse CSR tensor")
-    rowptr = a.crow_indices().to(torch.int32)
-    colind = a.col_indices().to(torch.int32)
+    rowptr, colind = _csr_index32(a)
     x = matfun(rowptr, colind, a.values().contiguous(), fn, param, precision)
     return torch.sparse_csr_tensor(a.crow_indices(), a.col_indices(), x, a.shape)

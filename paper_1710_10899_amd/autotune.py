@@ -1,11 +1,14 @@
 """Autotuner for the persistent large-order launches.
 
-Picks, per range of submatrix order, the number of workgroups per compute
-unit of the persistent kernels (FP64 and FP32 dense stages, and the
-tridiagonal eigensolver) by timing the library's own phases on seeded
-overlap-type workloads whose orders fall in each range. The result is a
-table file with lines "kind m_hi blocks_per_cu" (kind 0 = FP32 dense
-kernels, 1 = FP64 dense kernels, 2 = tridiagonal eigensolver); point the
+Picks, per range of submatrix order, the launch parameters of the
+persistent kernels by timing the library's own phases on seeded
+overlap-type workloads whose orders fall in each range: workgroups per
+compute unit of the FP64 and FP32 dense stages and of the tridiagonal
+eigensolver, and the panel width and workgroups per compute unit of the
+tridiagonal reduction (FP64 and FP32). The result is a table file with
+lines "kind m_hi value" (kind 0 / 1 = FP32 / FP64 dense kernels, 2 =
+tridiagonal eigensolver, 3 / 4 = FP64 / FP32 reduction panel width, 5 / 6
+= FP64 / FP32 reduction workgroups per compute unit); point the
 environment variable SUBMAT_TUNE_FILE at it (the library reads it at its
 first call, or when submat_set_option(SUBMAT_OPT_TUNE_FILE, 1) is called).
 
@@ -27,7 +30,10 @@ import time
 # m_hi = 2**30 covers every larger order
 DEFAULTS = [(1, 128, 8), (1, 256, 4), (1, 1024, 2), (1, 1 << 30, 1),
             (0, 128, 8), (0, 256, 4), (0, 1024, 2), (0, 1 << 30, 1),
-            (2, 256, 8), (2, 512, 6), (2, 1024, 4), (2, 1 << 30, 1)]
+            (2, 256, 8), (2, 512, 6), (2, 1024, 4), (2, 1 << 30, 1),
+            (3, 1 << 30, 16), (4, 1 << 30, 16), (5, 1 << 30, 2), (6, 1 << 30, 2)]
+# reduction candidates: (panel width, workgroups per compute unit)
+REDUCTION_CANDIDATES = ((8, 2), (16, 2), (24, 2), (32, 2), (16, 1), (24, 1), (32, 1), (48, 1))
 BUCKETS = (128, 256, 512, 1024)
 DENSE_PHASES = ("gather", "tridiagonalise", "back-transform", "apply-column", "adjoint")
 EIG_PHASES = ("tridiagonal-eig", "reorthogonalise")
@@ -117,6 +123,17 @@ def main(argv=None):
                 table = table_with(table, kind, bucket, bpc)
                 print(f"[autotune]   kind {kind}: " + ", ".join(f"{c}:{v:.2f}ms" for c, v in res.items())
                       + f" -> {bpc}", flush=True)
+            for kn, kc, precision in ((3, 5, "f64"), (4, 6, "f32_mixed")):
+                res = {}
+                for nb, pc in (REDUCTION_CANDIDATES if not args.quick else ((16, 2), (24, 1), (32, 1))):
+                    write_table(tmp, table_with(table_with(table, kn, bucket, nb), kc, bucket, pc))
+                    _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+                    res[(nb, pc)] = time_phases(csr, precision, ("tridiagonalise",), args.reps)
+                nb, pc = min(res, key=res.get)
+                table = table_with(table_with(table, kn, bucket, nb), kc, bucket, pc)
+                print(f"[autotune]   reduction {precision}: " + ", ".join(f"nb={a} x{b}:{v:.2f}ms"
+                                                                     for (a, b), v in res.items())
+                      + f" -> nb={nb} x{pc}", flush=True)
     finally:
         if old_env is None:
             os.environ.pop("SUBMAT_TUNE_FILE", None)

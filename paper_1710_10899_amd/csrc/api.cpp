@@ -31,6 +31,8 @@ struct Options {
   int small_max = 64;
   double ws_bytes = 0.0;
   double cluster_tol = 1e-5;
+  int deterministic = 0;   // adjoint assembled in a fixed order instead of by atomic adds
+  int plain_stride = 1;    // the per-column path computes every plain_stride-th column only
   uint64_t tune_gen = 0;   // bumped whenever the tuning table is reloaded
 };
 Options g_opt;
@@ -61,14 +63,29 @@ struct DeviceCtx {
   int device = -1;
   int num_cus = 0;
   int lds_limit = 65536;
-  DevBuf<int64_t> status;      // ST_NSLOTS slots
-  std::vector<int64_t> last_status;
+  // status counters (ST_NSLOTS int64 slots) per stream: a call resets and
+  // fills the block of the stream it runs on
+  std::map<uintptr_t, std::unique_ptr<DevBuf<int64_t>>> status;
   rocblas_handle blas = nullptr;  // dense products of the refinement, created on first use
   ~DeviceCtx() {
     if (blas) (void)rocblas_destroy_handle(blas);
   }
 };
 std::map<int, std::unique_ptr<DeviceCtx>> g_dev;
+
+// Status block of `stream` on this device, allocated (and zeroed) on first use.
+int stream_status(DeviceCtx* ctx, hipStream_t stream, int64_t** out) {
+  auto& slot = ctx->status[(uintptr_t)stream];
+  if (!slot) {
+    auto b = std::make_unique<DevBuf<int64_t>>();
+    int rc = b->alloc(ST_NSLOTS);
+    if (rc) return rc;
+    HIP_TRY(hipMemset(b->p, 0, ST_NSLOTS * sizeof(int64_t)));
+    slot = std::move(b);
+  }
+  *out = slot->p;
+  return SUBMAT_OK;
+}
 
 int get_ctx(DeviceCtx** out) {
   int dev = 0;
@@ -81,9 +98,6 @@ int get_ctx(DeviceCtx** out) {
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     ctx->num_cus = prop.multiProcessorCount;
     ctx->lds_limit = (int)prop.sharedMemPerBlock;
-    int rc = ctx->status.alloc(ST_NSLOTS);
-    if (rc) return rc;
-    HIP_TRY(hipMemset(ctx->status.p, 0, ST_NSLOTS * sizeof(int64_t)));
     it = g_dev.emplace(dev, std::move(ctx)).first;
   }
   *out = it->second.get();
@@ -112,6 +126,31 @@ struct GraphEntry {
   uint64_t stamp = 0;
 };
 
+// Device memory one stream's calls on a plan work in: slabs, vectors and
+// scratch of one chunk, per-item flags, work counters, and the graphs
+// captured for that stream. Calls on different streams never share one.
+struct Workspace {
+  uint64_t last_use = 0;
+  DevBuf<char> S, Q, W, dv, ev, tv, escr;
+  DevBuf<int32_t> flags;
+  DevBuf<int32_t> counters;
+  DevBuf<double> dsmall;   // deterministic adjoint: D of the one-wavefront columns
+  std::vector<GraphEntry> graphs;
+  uint64_t stamp = 0;
+  hipStream_t cap_stream = nullptr;
+  ~Workspace() {
+    for (auto& g : graphs) {
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+      if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+  int64_t bytes() const {
+    return (int64_t)(S.n + Q.n + W.n + dv.n + ev.n + tv.n + escr.n) + 4 * (int64_t)(flags.n + counters.n) +
+           8 * (int64_t)dsmall.n;
+  }
+};
+
 struct Plan {
   int device = 0;
   uint64_t last_use = 0;  // plan-cache clock at the last call with this pattern
@@ -133,37 +172,55 @@ struct Plan {
   std::vector<int64_t> h_sqoff, h_sdoff;
   std::vector<Chunk> chunks;
   int64_t saved_q_bytes = 0, saved_bytes = 0;
-  // workspace
-  DevBuf<char> S, Q, W, dv, ev, tv, escr;
-  DevBuf<int32_t> flags;
-  DevBuf<int32_t> counters;
+  // workspace sizes (bytes / elements) of one stream
+  int64_t ws_slab = 0, ws_vec = 0, ws_escr = 0;
+  int max_count = 0;
   int ncounters = 0;
-  // graphs
-  std::vector<GraphEntry> graphs;
-  uint64_t stamp = 0;
-  hipStream_t cap_stream = nullptr;
-  ~Plan() {
-    for (auto& g : graphs) {
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
-      if (g.graph) (void)hipGraphDestroy(g.graph);
-    }
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  int64_t small_d_elems = 0;          // sum of m^2 over the one-wavefront columns
+  // deterministic adjoint: per column, the phase that computes its D (0 = the
+  // one-wavefront launch, 1 + c = large-order chunk c) and where D lies
+  // (element offset and leading dimension)
+  DevBuf<int32_t> d_dphase, d_dld;
+  DevBuf<int64_t> d_doff;
+  std::map<uintptr_t, std::unique_ptr<Workspace>> ws;   // by stream
+  int64_t bytes() const {
+    int64_t b = 4 * (int64_t)(d_m.n + d_c.n + tpos.n + d_small.n + d_large.n + d_ldm.n + d_dphase.n + d_dld.n) +
+                8 * (int64_t)(d_off.n + d_voff.n + d_eoff.n + d_sqoff.n + d_sdoff.n + d_doff.n);
+    for (auto& w : ws) b += w.second->bytes();
+    return b;
   }
 };
 
 using PlanKey = std::tuple<int, uintptr_t, uintptr_t, int32_t, int64_t>;
 std::map<PlanKey, std::unique_ptr<Plan>> g_plans;
 
+// Saved buffers filled by a forward call: the plan, value type and precision
+// they were filled for. A backward call that names a buffer not recorded
+// here for its own pattern, type and precision is rejected (SUBMAT_ESAVED).
+struct SavedTag {
+  PlanKey key;
+  int32_t dtype = 0, precision = 0;
+};
+std::map<uintptr_t, SavedTag> g_saved;
+
+void forget_saved(const PlanKey& key) {
+  for (auto it = g_saved.begin(); it != g_saved.end();) {
+    if (it->second.key == key) it = g_saved.erase(it);
+    else ++it;
+  }
+}
+
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 // Plan cache bookkeeping: a use clock for least-recently-used eviction and
-// the device bytes a plan's workspace holds.
+// the device bytes a plan and its workspaces hold.
 uint64_t g_plan_clock = 0;
 
-int64_t plan_bytes(const Plan& P) {
-  return (int64_t)(P.S.n + P.Q.n + P.W.n + P.dv.n + P.ev.n + P.tv.n + P.escr.n) +
-         4 * (int64_t)(P.tpos.n + P.flags.n + P.counters.n);
-}
+int64_t plan_bytes(const Plan& P) { return P.bytes(); }
+
+// Workspaces kept per plan: calls on more streams than this drop the least
+// recently used one (freeing waits for the device).
+constexpr size_t kMaxWorkspaces = 4;
 
 // Drop cached plans of this device, least recently used first, until the
 // others hold at most `keep` bytes (all of them for keep < 0). Freeing
@@ -178,6 +235,7 @@ void evict_plans(int device, int64_t keep) {
       if (victim == g_plans.end() || p->second->last_use < victim->second->last_use) victim = p;
     }
     if (victim == g_plans.end() || (keep >= 0 && held <= keep)) return;
+    forget_saved(victim->first);
     g_plans.erase(victim);
   }
 }
@@ -297,26 +355,38 @@ int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int
   P.saved_q_bytes = sq;
   P.saved_bytes = nl ? (sq + sd + 4 * (int64_t)nl) : 0;
 
-  int64_t ws_slab = 0, ws_vec = 0, ws_escr = 0;
-  int max_count = 0;
   for (auto& c : P.chunks) {
-    ws_slab = std::max(ws_slab, c.slab_bytes);
-    ws_vec = std::max(ws_vec, c.vec_bytes);
-    ws_escr = std::max(ws_escr, c.escr_bytes);
-    max_count = std::max(max_count, c.count);
+    P.ws_slab = std::max(P.ws_slab, c.slab_bytes);
+    P.ws_vec = std::max(P.ws_vec, c.vec_bytes);
+    P.ws_escr = std::max(P.ws_escr, c.escr_bytes);
+    P.max_count = std::max(P.max_count, c.count);
   }
+  // where the deterministic adjoint finds each column's D: the one-wavefront
+  // columns in a buffer of their own (leading dimension m), the large-order
+  // columns in their chunk's S slab (leading dimension ldm)
+  std::vector<int32_t> dphase(n, -1), dld(n, 0);
+  std::vector<int64_t> doff(n, 0);
+  for (int32_t j : P.small_items) {
+    dphase[j] = 0;
+    dld[j] = P.h_m[j];
+    doff[j] = P.small_d_elems;
+    P.small_d_elems += (int64_t)P.h_m[j] * P.h_m[j];
+  }
+  for (int ci = 0; ci < (int)P.chunks.size(); ++ci)
+    for (int g = P.chunks[ci].start; g < P.chunks[ci].start + P.chunks[ci].count; ++g) {
+      const int32_t j = P.large_items[g];
+      dphase[j] = 1 + ci;
+      dld[j] = ldm[g];
+      doff[j] = off[g];   // bytes; the kernel divides by the element size
+    }
   if ((rc = P.d_small.alloc(P.small_items.size())) || (rc = P.d_large.alloc(nl)) || (rc = P.d_ldm.alloc(nl)) ||
       (rc = P.d_off.alloc(nl)) || (rc = P.d_voff.alloc(nl)) || (rc = P.d_eoff.alloc(nl)) ||
-      (rc = P.d_sqoff.alloc(nl)) || (rc = P.d_sdoff.alloc(nl)))
-    return rc;
-  if ((rc = P.S.alloc(ws_slab)) || (rc = P.Q.alloc(ws_slab)) || (rc = P.W.alloc(ws_slab)) ||
-      (rc = P.dv.alloc(ws_vec)) || (rc = P.ev.alloc(ws_vec)) || (rc = P.tv.alloc(ws_vec)) ||
-      (rc = P.escr.alloc(ws_escr)) || (rc = P.flags.alloc(std::max(max_count, 1))))
+      (rc = P.d_sqoff.alloc(nl)) || (rc = P.d_sdoff.alloc(nl)) || (rc = P.d_dphase.alloc(n)) ||
+      (rc = P.d_dld.alloc(n)) || (rc = P.d_doff.alloc(n)))
     return rc;
   // one work counter per persistent launch of the longest sequence (the
   // per-column path launches up to 7 kernels per column)
   P.ncounters = 64 + 32 * (int)P.chunks.size() + 8 * n;
-  if ((rc = P.counters.alloc(P.ncounters))) return rc;
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (!bytes) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
@@ -329,13 +399,69 @@ int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int
   HIP_TRY(up(P.d_eoff.p, eoff.data(), nl * 8));
   HIP_TRY(up(P.d_sqoff.p, P.h_sqoff.data(), nl * 8));
   HIP_TRY(up(P.d_sdoff.p, P.h_sdoff.data(), nl * 8));
+  HIP_TRY(up(P.d_dphase.p, dphase.data(), (size_t)n * 4));
+  HIP_TRY(up(P.d_dld.p, dld.data(), (size_t)n * 4));
+  HIP_TRY(up(P.d_doff.p, doff.data(), (size_t)n * 8));
   HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
   P.last_use = ++g_plan_clock;
   *out = plan.get();
   g_plans.emplace(key, std::move(plan));
   return SUBMAT_OK;
 }
+
+int alloc_workspace(Plan& P, Workspace& W) {
+  int rc;
+  if ((rc = W.S.alloc(P.ws_slab)) || (rc = W.Q.alloc(P.ws_slab)) || (rc = W.W.alloc(P.ws_slab)) ||
+      (rc = W.dv.alloc(P.ws_vec)) || (rc = W.ev.alloc(P.ws_vec)) || (rc = W.tv.alloc(P.ws_vec)) ||
+      (rc = W.escr.alloc(P.ws_escr)) || (rc = W.flags.alloc(std::max(P.max_count, 1))) ||
+      (rc = W.counters.alloc(P.ncounters)))
+    return rc;
+  HIP_TRY(hipStreamCreateWithFlags(&W.cap_stream, hipStreamNonBlocking));
+  return SUBMAT_OK;
+}
+
+// The workspace of `stream` on plan P, allocated on the stream's first call.
+// When it does not fit, the other plans of the device, then this plan's
+// other workspaces, are dropped (least recently used first) and the
+// allocation is retried.
+int get_workspace(Plan& P, hipStream_t stream, Workspace** out) {
+  const uintptr_t key = (uintptr_t)stream;
+  auto it = P.ws.find(key);
+  if (it == P.ws.end()) {
+    if (P.ws.size() >= kMaxWorkspaces) {
+      auto old = std::min_element(P.ws.begin(), P.ws.end(), [](const auto& a, const auto& b) {
+        return a.second->last_use < b.second->last_use;
+      });
+      P.ws.erase(old);
+    }
+    auto w = std::make_unique<Workspace>();
+    int rc = alloc_workspace(P, *w);
+    if (rc == SUBMAT_ENOMEM) {
+      (void)hipGetLastError();
+      w.reset();
+      for (auto p = g_plans.begin(); p != g_plans.end();) {
+        if (p->second.get() != &P && p->second->device == P.device) {
+          forget_saved(p->first);
+          p = g_plans.erase(p);
+        } else {
+          ++p;
+        }
+      }
+      P.ws.clear();
+      w = std::make_unique<Workspace>();
+      rc = alloc_workspace(P, *w);
+    }
+    if (rc) return rc;
+    it = P.ws.emplace(key, std::move(w)).first;
+  }
+  it->second->last_use = ++g_plan_clock;
+  *out = it->second.get();
+  return SUBMAT_OK;
+}
+
+// Drops the cached plans (all workspaces and graphs) and Krylov data of one
+// pattern on the current device; returns whether any existed.
+bool release_pattern(int device, const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz);
 
 // ------------------------------------------------------- Krylov patterns
 // Validated pattern (same device check as the plan), the transpose position
@@ -406,6 +532,7 @@ struct Call {
   void* ga;         // backward output
   char* saved;      // optional saved buffer
   bool bwd;
+  int det = 0;      // backward: deterministic assembly
 };
 
 struct Timer {
@@ -449,7 +576,7 @@ int persistent_grid(DeviceCtx* ctx, int n_items, int per_cu) {
   return g < 1 ? 1 : g;
 }
 
-LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, int max_m) {
+LargeArgs make_large(Plan& P, Workspace& W, const Call& c, int chunk, int g_first, int count, int max_m) {
   LargeArgs a{};
   a.rowptr = P.rowptr;
   a.colind = P.colind;
@@ -470,24 +597,25 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
   } else {
     a.qoff = P.d_off.p + g_first;
     a.doff = P.d_voff.p + g_first;
-    a.Q = P.Q.p;
-    a.d = P.dv.p;
+    a.Q = W.Q.p;
+    a.d = W.dv.p;
   }
   a.n_items = count;
   a.max_m = max_m;
-  a.S = P.S.p;
-  a.W = P.W.p;
-  a.e = P.ev.p;
-  a.tau = P.tv.p;
-  a.escr = P.escr.p;
+  a.S = W.S.p;
+  a.W = W.W.p;
+  a.e = W.ev.p;
+  a.tau = W.tv.p;
+  a.escr = W.escr.p;
   a.flags = (c.saved ? (int32_t*)(c.saved + P.saved_bytes - 4 * (int64_t)P.large_items.size()) + g_first
-                     : P.flags.p + (g_first - P.chunks[chunk].start));
+                     : W.flags.p + (g_first - P.chunks[chunk].start));
   a.fn = c.fn;
   a.kappa_max = g_opt.kappa_max;
   a.cluster_tol = g_opt.cluster_tol;
   a.x = c.x;
   a.gx = c.gx;
   a.ga = c.ga;
+  a.det = c.bwd ? c.det : 0;
   return a;
 }
 
@@ -495,17 +623,17 @@ LargeArgs make_large(Plan& P, const Call& c, int chunk, int g_first, int count, 
 // of `chunk`, in FP64 or FP32. `only_flagged` restricts it to the items the
 // FP32 pass sent to FP64. With a saved buffer in the backward, only the
 // adjoint runs.
-int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, int& ctr, int chunk, int g_first,
-              int count, int max_m, int fp64, int only_flagged, bool per_column) {
-  LargeArgs a = make_large(P, c, chunk, g_first, count, max_m);
-  a.status = ctx->status.p;
+int run_large(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* status, hipStream_t s, Timer& tm,
+              int& ctr, int chunk, int g_first, int count, int max_m, int fp64, int only_flagged, bool per_column) {
+  LargeArgs a = make_large(P, W, c, chunk, g_first, count, max_m);
+  a.status = status;
   a.lds_limit = ctx->lds_limit;
   a.fp64 = fp64;
   a.only_flagged = only_flagged;
   const int tune_cu = per_column ? 0 : tuned_blocks_per_cu(max_m, fp64);
   a.grid = per_column ? 1 : persistent_grid(ctx, count, tune_cu);
   const int ph = only_flagged ? PH_FALLBACK : -1;
-  auto next = [&]() { a.work_ctr = P.counters.p + (ctr++ % P.ncounters); };
+  auto next = [&]() { a.work_ctr = W.counters.p + (ctr++ % P.ncounters); };
   // Kernels whose registers and LDS leave room for more workgroups per
   // compute unit than the tuned value get at least that many (measured on
   // the overlap workloads: the gather, the column and the
@@ -520,8 +648,17 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
   const bool eig = !(c.bwd && c.saved);
   if (eig) {
     next(); HIP_SEQ(ph < 0 ? PH_GATHER : ph, launch_gather_large(with_grid(8), s));
-    // the reduction runs two 4-wave workgroups per compute unit
-    next(); HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(with_grid(reduction_blocks_per_cu()), s));
+    // the reduction: panel width and workgroups per compute unit from the
+    // tuning table (its LDS panel copy is sized for that many)
+    {
+      LargeArgs r = with_grid(0);
+      r.nb = tuned_reduction_nb(max_m, fp64);
+      r.red_per_cu = tuned_reduction_per_cu(max_m, fp64);
+      if (!per_column) r.grid = persistent_grid(ctx, count, r.red_per_cu);
+      next();
+      r.work_ctr = a.work_ctr;
+      HIP_SEQ(ph < 0 ? PH_TRIDIAG : ph, launch_tridiagonalise(r, s));
+    }
     {
       // the eigensolver's workgroups share a compute unit's LDS
       LargeArgs b = a;
@@ -533,17 +670,38 @@ int run_large(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm, 
       HIP_SEQ(ph < 0 ? PH_EIG : ph, launch_tridiag_eig(b, s));
     }
     next(); HIP_SEQ(ph < 0 ? PH_ORTH : ph, launch_eig_orth(with_grid(4), s));
-    next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(with_grid(back_blocks_per_cu()), s));
+    // the eigenvector matrix Q = Q1 Z is formed only where it is used: by the
+    // adjoint, or kept in a saved buffer for a later adjoint
+    if (c.bwd || c.saved) {
+      next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(with_grid(back_blocks_per_cu()), s));
+    }
   }
   next();
   if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(with_grid(adjoint_blocks_per_cu()), s));
-  else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
+  else if (c.saved) HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
+  else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_column_factored(with_grid(column_waves_per_cu()), s));
   return SUBMAT_OK;
 }
 
-int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& tm) {
+DetReduceArgs det_args(const Plan& P, const Call& c, int phase, const void* base, int bytes_off) {
+  DetReduceArgs d{};
+  d.rowptr = P.rowptr;
+  d.colind = P.colind;
+  d.tpos = P.tpos.p;
+  d.n = P.n;
+  d.phase = phase;
+  d.dphase = P.d_dphase.p;
+  d.dld = P.d_dld.p;
+  d.doff = P.d_doff.p;
+  d.base = base;
+  d.bytes_off = bytes_off;
+  d.ga = c.ga;
+  return d;
+}
+
+int run_sequence(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* status, hipStream_t s, Timer& tm) {
   int ctr = 0;
-  HIP_SEQ(PH_RESET, launch_reset_status(ctx->status.p, P.counters.p, P.ncounters, s));
+  HIP_SEQ(PH_RESET, launch_reset_status(status, W.counters.p, P.ncounters, s));
   if (c.bwd) HIP_SEQ(PH_RESET, launch_fill_zero(c.ga, P.nnz * (c.vdtype == 0 ? 8 : 4), s));
   const bool plain = c.precision == SUBMAT_PREC_F64_PLAIN;
   const int mixed = c.precision == SUBMAT_PREC_F32_MIXED;
@@ -561,37 +719,50 @@ int run_sequence(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s, Timer& t
     sa.x = c.bwd ? nullptr : c.x;
     sa.gx = c.bwd ? c.gx : nullptr;
     sa.ga = c.bwd ? c.ga : nullptr;
-    sa.status = ctx->status.p;
+    sa.status = status;
+    const bool det_small = c.bwd && c.det;
+    if (det_small) {
+      if (W.dsmall.n < (size_t)P.small_d_elems) return SUBMAT_EINVAL;  // sized by run_call
+      sa.dout = W.dsmall.p;
+      sa.doff = P.d_doff.p;
+      sa.dld = P.d_dld.p;
+    }
     if (!plain) {
       sa.items = P.d_small.p;
       sa.n_items = (int)P.small_items.size();
       sa.mmax = P.small_mmax;
       sa.grid = persistent_grid(ctx, sa.n_items, 8);
-      sa.work_ctr = P.counters.p + (ctr++ % P.ncounters);
+      sa.work_ctr = W.counters.p + (ctr++ % P.ncounters);
       HIP_SEQ(PH_SMALL, launch_small(sa, s));
     } else {
-      for (size_t i = 0; i < P.small_items.size(); ++i) {
+      for (size_t i = 0; i < P.small_items.size(); i += g_opt.plain_stride) {
         sa.items = P.d_small.p + i;
         sa.n_items = 1;
         sa.mmax = P.h_m[P.small_items[i]];
         sa.grid = 1;
-        sa.work_ctr = P.counters.p + (ctr++ % P.ncounters);
+        sa.work_ctr = W.counters.p + (ctr++ % P.ncounters);
         HIP_SEQ(PH_SMALL, launch_small(sa, s));
       }
     }
+    if (det_small) HIP_SEQ(PH_ADJOINT, launch_adjoint_reduce(det_args(P, c, 0, W.dsmall.p, 0), c.vdtype,
+                                                              ctx->num_cus, s));
   }
   // large-order bucket, chunk by chunk
   for (int ci = 0; ci < (int)P.chunks.size(); ++ci) {
     const Chunk& ch = P.chunks[ci];
     if (plain) {
+      // large items are numbered across chunks in one order (largest first)
       for (int g = ch.start; g < ch.start + ch.count; ++g)
-        SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, g, 1, P.h_m[P.large_items[g]], 1, 0, true));
+        if (g % g_opt.plain_stride == 0)
+          SEQ_TRY(run_large(P, W, ctx, c, status, s, tm, ctr, ci, g, 1, P.h_m[P.large_items[g]], 1, 0, true));
     } else if (!mixed) {
-      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 0, false));
+      SEQ_TRY(run_large(P, W, ctx, c, status, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 0, false));
     } else {
-      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 0, 0, false));
-      SEQ_TRY(run_large(P, ctx, c, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 1, false));
+      SEQ_TRY(run_large(P, W, ctx, c, status, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 0, 0, false));
+      SEQ_TRY(run_large(P, W, ctx, c, status, s, tm, ctr, ci, ch.start, ch.count, ch.max_m, 1, 1, false));
     }
+    if (c.bwd && c.det)
+      HIP_SEQ(PH_ADJOINT, launch_adjoint_reduce(det_args(P, c, 1 + ci, W.W.p, 1), c.vdtype, ctx->num_cus, s));
   }
   return SUBMAT_OK;
 }
@@ -602,30 +773,31 @@ uintptr_t fn_alpha_bits(const SpecFn& f) {
   return (uintptr_t)b;
 }
 
-int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
+int launch_graph(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* status, hipStream_t s) {
   std::vector<uintptr_t> key = {(uintptr_t)c.vals, (uintptr_t)c.vdtype, (uintptr_t)c.fn.kind, (uintptr_t)c.fn.p,
                                 fn_alpha_bits(c.fn), (uintptr_t)c.precision,
                                 (uintptr_t)c.x, (uintptr_t)c.gx, (uintptr_t)c.ga, (uintptr_t)c.saved,
-                                (uintptr_t)c.bwd, (uintptr_t)(g_opt.kappa_max * 1e3), (uintptr_t)(g_opt.cluster_tol * 1e12),
+                                (uintptr_t)c.bwd, (uintptr_t)c.det, (uintptr_t)(g_opt.kappa_max * 1e3),
+                                (uintptr_t)(g_opt.cluster_tol * 1e12),
                                 (uintptr_t)g_opt.tune_gen};
   GraphEntry* hit = nullptr;
-  for (auto& g : P.graphs)
+  for (auto& g : W.graphs)
     if (g.key == key) hit = &g;
   if (!hit) {
-    if (P.graphs.size() >= 8) {
-      auto old = std::min_element(P.graphs.begin(), P.graphs.end(),
+    if (W.graphs.size() >= 8) {
+      auto old = std::min_element(W.graphs.begin(), W.graphs.end(),
                                   [](const GraphEntry& a, const GraphEntry& b) { return a.stamp < b.stamp; });
       if (old->exec) (void)hipGraphExecDestroy(old->exec);
       if (old->graph) (void)hipGraphDestroy(old->graph);
-      P.graphs.erase(old);
+      W.graphs.erase(old);
     }
     GraphEntry ge;
     ge.key = key;
     Timer off;
-    HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
-    int rc = run_sequence(P, ctx, c, P.cap_stream, off);
+    HIP_TRY(hipStreamBeginCapture(W.cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = run_sequence(P, W, ctx, c, status, W.cap_stream, off);
     hipGraph_t graph = nullptr;
-    hipError_t ec = hipStreamEndCapture(P.cap_stream, &graph);
+    hipError_t ec = hipStreamEndCapture(W.cap_stream, &graph);
     if (rc != SUBMAT_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return rc;
@@ -636,10 +808,10 @@ int launch_graph(Plan& P, DeviceCtx* ctx, const Call& c, hipStream_t s) {
       (void)hipGraphDestroy(graph);
       return SUBMAT_EHIP;
     }
-    P.graphs.push_back(ge);
-    hit = &P.graphs.back();
+    W.graphs.push_back(ge);
+    hit = &W.graphs.back();
   }
-  hit->stamp = ++P.stamp;
+  hit->stamp = ++W.stamp;
   HIP_TRY(hipGraphLaunch(hit->exec, s));
   return SUBMAT_OK;
 }
@@ -678,19 +850,53 @@ int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nn
   Plan* P = nullptr;
   SEQ_TRY(build_plan(rowptr, colind, n, nnz, s, ctx, &P));
   if (c.saved && c.precision == SUBMAT_PREC_F64_PLAIN) c.saved = nullptr;
+  const PlanKey key{ctx->device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
+  if (c.saved && c.bwd) {
+    auto t = g_saved.find((uintptr_t)c.saved);
+    if (t == g_saved.end() || !(t->second.key == key) || t->second.dtype != c.vdtype ||
+        t->second.precision != c.precision)
+      return SUBMAT_ESAVED;
+  }
+  Workspace* W = nullptr;
+  SEQ_TRY(get_workspace(*P, s, &W));
+  // buffers a call needs are allocated here, never while a graph is captured
+  if (c.bwd && c.det && W->dsmall.n < (size_t)P->small_d_elems) SEQ_TRY(W->dsmall.alloc(P->small_d_elems));
+  int64_t* status = nullptr;
+  SEQ_TRY(stream_status(ctx, s, &status));
+  int rc;
   if (timer) {
     timer->s = s;
     timer->on = true;
     HIP_TRY(hipEventCreate(&timer->a));
     HIP_TRY(hipEventCreate(&timer->b));
-    int rc = run_sequence(*P, ctx, c, s, *timer);
+    rc = run_sequence(*P, *W, ctx, c, status, s, *timer);
     (void)hipEventDestroy(timer->a);
     (void)hipEventDestroy(timer->b);
-    return rc;
+  } else if (g_opt.use_graph && c.precision != SUBMAT_PREC_F64_PLAIN) {
+    rc = launch_graph(*P, *W, ctx, c, status, s);
+  } else {
+    Timer off;
+    rc = run_sequence(*P, *W, ctx, c, status, s, off);
   }
-  if (g_opt.use_graph && c.precision != SUBMAT_PREC_F64_PLAIN) return launch_graph(*P, ctx, c, s);
-  Timer off;
-  return run_sequence(*P, ctx, c, s, off);
+  if (rc == SUBMAT_OK && c.saved && !c.bwd) g_saved[(uintptr_t)c.saved] = SavedTag{key, c.vdtype, c.precision};
+  return rc;
+}
+
+bool release_pattern(int device, const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz) {
+  const PlanKey key{device, (uintptr_t)rowptr, (uintptr_t)colind, n, nnz};
+  bool found = false;
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    forget_saved(key);
+    g_plans.erase(it);
+    found = true;
+  }
+  auto kt = g_kry.find(key);
+  if (kt != g_kry.end()) {
+    g_kry.erase(kt);
+    found = true;
+  }
+  return found;
 }
 
 // ------------------------------------------------------------- Krylov loops
@@ -935,7 +1141,7 @@ int submat_matfun_bwd(const int32_t* rowptr, const int32_t* colind, const void* 
   if (rc) return rc;
   if (!grad_x || !grad_a) return SUBMAT_EINVAL;
   std::lock_guard<std::mutex> lk(g_mu);
-  Call c{vals, dtype, f, precision, nullptr, grad_x, grad_a, (char*)saved, true};
+  Call c{vals, dtype, f, precision, nullptr, grad_x, grad_a, (char*)saved, true, g_opt.deterministic};
   return run_call(rowptr, colind, n, nnz, c, stream, nullptr);
 }
 
@@ -972,9 +1178,11 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
   DeviceCtx* ctx = nullptr;
   int rc = get_ctx(&ctx);
   if (rc) return rc;
+  int64_t* st = nullptr;
+  if ((rc = stream_status(ctx, (hipStream_t)stream, &st))) return rc;
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   int64_t h[ST_NSLOTS] = {0};
-  HIP_TRY(hipMemcpy(h, ctx->status.p, sizeof(h), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(h, st, sizeof(h), hipMemcpyDeviceToHost));
   if (n_nonpositive) *n_nonpositive = h[ST_NONPOS];
   if (n_fallback) *n_fallback = h[ST_FALLBACK];
   if (n_unconverged) *n_unconverged = h[ST_UNCONV];
@@ -987,8 +1195,10 @@ int submat_query_counters(void* stream, int64_t* out, int32_t n) {
   DeviceCtx* ctx = nullptr;
   int rc = get_ctx(&ctx);
   if (rc) return rc;
+  int64_t* st = nullptr;
+  if ((rc = stream_status(ctx, (hipStream_t)stream, &st))) return rc;
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-  HIP_TRY(hipMemcpy(out, ctx->status.p, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(out, st, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost));
   return SUBMAT_OK;
 }
 
@@ -1006,11 +1216,13 @@ int submat_set_option(int32_t key, double value) {
       if (value < 1 || value > 64) return SUBMAT_EINVAL;
       g_opt.small_max = (int)value;
       g_plans.clear();
+      g_saved.clear();
       return SUBMAT_OK;
     case SUBMAT_OPT_WS_BYTES:
       if (value < 0) return SUBMAT_EINVAL;
       g_opt.ws_bytes = value;
       g_plans.clear();
+      g_saved.clear();
       return SUBMAT_OK;
     case SUBMAT_OPT_CLUSTER_TOL:
       if (!(value >= 0.0 && value < 1.0)) return SUBMAT_EINVAL;
@@ -1020,6 +1232,14 @@ int submat_set_option(int32_t key, double value) {
       if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
       reload_tuning(value == 1.0);
       g_opt.tune_gen++;
+      return SUBMAT_OK;
+    case SUBMAT_OPT_DETERMINISTIC:
+      if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
+      g_opt.deterministic = (int)value;
+      return SUBMAT_OK;
+    case SUBMAT_OPT_PLAIN_STRIDE:
+      if (!(value >= 1.0 && value <= 1e9) || value != std::floor(value)) return SUBMAT_EINVAL;
+      g_opt.plain_stride = (int)value;
       return SUBMAT_OK;
     default:
       return SUBMAT_EINVAL;
@@ -1035,6 +1255,8 @@ double submat_get_option(int32_t key) {
     case SUBMAT_OPT_WS_BYTES: return g_opt.ws_bytes;
     case SUBMAT_OPT_CLUSTER_TOL: return g_opt.cluster_tol;
     case SUBMAT_OPT_TUNE_FILE: return tuning_from_file() ? 1.0 : 0.0;
+    case SUBMAT_OPT_DETERMINISTIC: return g_opt.deterministic;
+    case SUBMAT_OPT_PLAIN_STRIDE: return g_opt.plain_stride;
     default: return NAN;
   }
 }
@@ -1060,6 +1282,16 @@ void submat_release(void) {
   (void)hipDeviceSynchronize();
   g_plans.clear();
   g_kry.clear();
+  g_saved.clear();
+}
+
+int submat_release_pattern(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nnz) {
+  if (!rowptr || !colind) return SUBMAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  (void)release_pattern(dev, rowptr, colind, n, nnz);
+  return SUBMAT_OK;
 }
 
 int submat_spmv(const int32_t* rowptr, const int32_t* colind, const double* vals, int32_t n, int64_t nnz,
@@ -1115,7 +1347,7 @@ int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_val
                   (hipStream_t)stream);
 }
 
-int32_t submat_version(void) { return 120; }
+int32_t submat_version(void) { return 130; }
 
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                        int32_t fn, double param, int32_t dtype, int32_t precision, void* x_vals,
@@ -1131,7 +1363,7 @@ int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void*
   rc = run_call(rowptr, colind, n, nnz, c, stream, &tm);
   if (rc) return rc;
   if (grad_x && grad_a) {
-    Call cb{vals, dtype, f, precision, nullptr, grad_x, grad_a, nullptr, true};
+    Call cb{vals, dtype, f, precision, nullptr, grad_x, grad_a, nullptr, true, g_opt.deterministic};
     rc = run_call(rowptr, colind, n, nnz, cb, stream, &tm);
     if (rc) return rc;
   }

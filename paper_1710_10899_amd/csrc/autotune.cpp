@@ -1,12 +1,16 @@
 // Tuning table for the persistent large-order launches.
 //
-// The table maps an upper bound on the submatrix order to the number of
-// workgroups per compute unit: kind 0 = FP32 persistent kernels, kind 1 =
-// FP64 persistent kernels, kind 2 = tridiagonal eigensolver (capped by its
-// LDS use at launch). Defaults come from LDS and
-// register use of the kernels; a file written by the package's autotune
-// script (environment variable SUBMAT_TUNE_FILE, lines
-// "kind m_hi blocks_per_cu") overrides them.
+// The table maps an upper bound on the submatrix order to a launch
+// parameter, by kind:
+//   0 / 1  workgroups per compute unit of the FP32 / FP64 persistent kernels
+//   2      workgroups per compute unit of the tridiagonal eigensolver
+//          (capped by its LDS use at launch)
+//   3 / 4  panel width of the FP64 / FP32 tridiagonal reduction (even, 2..48)
+//   5 / 6  workgroups per compute unit the FP64 / FP32 reduction is laid
+//          out for (1 or 2: its LDS panel copy takes the rest of the share)
+// Defaults are the gfx950 measurements on the overlap workloads; a file
+// written by the package's autotune script (environment variable
+// SUBMAT_TUNE_FILE, lines "kind m_hi value") overrides them.
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -29,15 +33,21 @@ std::mutex g_tmu;
 void load_locked(bool use_file) {
   g_table = {{1, 128, 8}, {1, 256, 4}, {1, 1024, 2}, {1, 1 << 30, 1},
              {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1},
-             {2, 256, 8}, {2, 512, 6}, {2, 1024, 4}, {2, 1 << 30, 1}};
+             {2, 256, 8}, {2, 512, 6}, {2, 1024, 4}, {2, 1 << 30, 1},
+             {3, 1 << 30, 16}, {4, 1 << 30, 16}, {5, 1 << 30, 2}, {6, 1 << 30, 2}};
   g_from_file = false;
   const char* path = use_file ? std::getenv("SUBMAT_TUNE_FILE") : nullptr;
   if (path && *path) {
     if (FILE* f = std::fopen(path, "r")) {
       std::vector<Entry> t;
       Entry e;
-      while (std::fscanf(f, "%d %d %d", &e.fp64, &e.m_hi, &e.bpc) == 3)
-        if (e.bpc >= 1 && e.bpc <= 32 && e.m_hi >= 1 && e.fp64 >= 0 && e.fp64 <= 2) t.push_back(e);
+      while (std::fscanf(f, "%d %d %d", &e.fp64, &e.m_hi, &e.bpc) == 3) {
+        bool ok = e.m_hi >= 1 && e.fp64 >= 0 && e.fp64 <= 6;
+        if (e.fp64 <= 2) ok = ok && e.bpc >= 1 && e.bpc <= 32;
+        else if (e.fp64 <= 4) ok = ok && e.bpc >= 2 && e.bpc <= 48 && !(e.bpc & 1);
+        else ok = ok && (e.bpc == 1 || e.bpc == 2);
+        if (ok) t.push_back(e);
+      }
       std::fclose(f);
       if (!t.empty()) {
         g_table = t;
@@ -61,10 +71,10 @@ bool tuning_from_file() {
   return g_from_file;
 }
 
-static int lookup(int kind, int max_m) {
+static int lookup(int kind, int max_m, int fallback = 1) {
   std::lock_guard<std::mutex> lk(g_tmu);
   if (!g_loaded) load_locked(true);
-  int best = 1, best_hi = 1 << 30;
+  int best = fallback, best_hi = 1 << 30;
   bool found = false;
   for (const Entry& e : g_table) {
     if (e.fp64 != kind || max_m > e.m_hi) continue;
@@ -80,5 +90,9 @@ static int lookup(int kind, int max_m) {
 int tuned_blocks_per_cu(int max_m, int fp64) { return lookup(fp64 ? 1 : 0, max_m); }
 
 int tuned_eig_blocks_per_cu(int max_m) { return lookup(2, max_m); }
+
+int tuned_reduction_nb(int max_m, int fp64) { return lookup(fp64 ? 3 : 4, max_m, 16); }
+
+int tuned_reduction_per_cu(int max_m, int fp64) { return lookup(fp64 ? 5 : 6, max_m, 2); }
 
 }  // namespace submat

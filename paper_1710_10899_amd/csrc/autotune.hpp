@@ -11,6 +11,11 @@ int tuned_blocks_per_cu(int max_m, int fp64);
 // workgroups of a compute unit share its LDS).
 int tuned_eig_blocks_per_cu(int max_m);
 
+// Panel width and workgroups per compute unit of the tridiagonal reduction
+// for a chunk whose largest order is max_m, in FP64 or FP32.
+int tuned_reduction_nb(int max_m, int fp64);
+int tuned_reduction_per_cu(int max_m, int fp64);
+
 // Reloads the table: from the file named by SUBMAT_TUNE_FILE when use_file
 // (built-in defaults when unset, unreadable or empty), else the defaults.
 void reload_tuning(bool use_file);

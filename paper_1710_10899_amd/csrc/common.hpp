@@ -82,6 +82,29 @@ __device__ __forceinline__ double spec_divdiff(double xk, double xl, double pwl,
   return POW ? power_divdiff(xk, xl, pwl, f.alpha) : root_divdiff(xk, xl, f);
 }
 
+// Lane exchange by DPP (the VALU reads its operand from another lane of the
+// same row of 16 lanes, without an LDS round trip). gfx9 DPP control codes:
+// quad_perm [l0, l1, l2, l3] = l0 | l1 << 2 | l2 << 4 | l3 << 6;
+// row_half_mirror (lane i <-> 7 - i within each group of 8) = 0x141.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8). Each
+// step adds the partner lane's value; IEEE addition is commutative, so every
+// lane of a group ends with the same bits.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
+  if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: the other quad of the 8
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

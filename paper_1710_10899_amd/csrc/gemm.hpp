@@ -106,6 +106,18 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
   for (int i0 = 0; i0 < M; i0 += BM) {
     for (int j0 = 0; j0 < N; j0 += BN) {
       if (LOWER && j0 >= i0 + BM) continue;
+      // 16 x 16 output blocks of this wave that hold no element of C (past
+      // M or N, or above the diagonal for LOWER) take no MFMA: the tests
+      // are uniform over the wave
+      bool live[TM][TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int r0 = i0 + wr * WM + a * 16, c0 = j0 + wc * WN + b * 16;
+          live[a][b] = r0 < M && c0 < N && (!LOWER || c0 <= r0 + 15);
+        }
+      }
       acc_t acc[TM][TN];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
@@ -157,7 +169,8 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
 #pragma unroll
           for (int a = 0; a < TM; ++a)
 #pragma unroll
-            for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < TN; ++b)
+              if (live[a][b]) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
         }
       };
       if (PF >= 1) fetch(0, 0);
@@ -215,6 +228,15 @@ __device__ void wg_syr2k_lower(int M, int K, T alpha, const T* __restrict__ V, i
   for (int i0 = 0; i0 < M; i0 += BM) {
     for (int j0 = 0; j0 < M; j0 += BN) {
       if (j0 >= i0 + BM) continue;
+      bool live[2][2];  // this wave's 16 x 16 blocks that meet the lower triangle of C
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int r0 = i0 + wr * 32 + a * 16, c0 = j0 + wc * 32 + b * 16;
+          live[a][b] = r0 < M && c0 < M && c0 <= r0 + 15;
+        }
+      }
       acc_t acc[2][2];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -267,7 +289,8 @@ __device__ void wg_syr2k_lower(int M, int K, T alpha, const T* __restrict__ V, i
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < 2; ++b)
+              if (live[a][b]) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
         }
       }
 #pragma unroll

@@ -12,6 +12,7 @@ enum StatusSlot : int {
   ST_FALLBACK = 1,    // submatrices redone in FP64 by the mixed path
   ST_UNCONV = 2,      // eigensolver did not converge
   ST_INVITER = 3,     // eigenvectors computed by inverse iteration (eigenvalue clusters)
+  ST_STALE = 4,       // columns whose order exceeds what the plan was built for (NaN output)
   ST_NSLOTS = 64,
 };
 
@@ -58,8 +59,27 @@ struct SmallArgs {
   int64_t* status;
   int32_t* work_ctr;     // zeroed before the launch
   int grid;              // persistent grid size
+  double* dout;          // backward, deterministic: D_j is written here (m x m, column-major)
+  const int64_t* doff;   //   at dout + doff[j] instead of being scatter-added,
+  const int32_t* dld;    //   in a slot planned for order dld[j]
 };
 hipError_t launch_small(const SmallArgs& a, hipStream_t s);
+
+// ---- deterministic adjoint assembly (adjoint_reduce.hip) ----
+struct DetReduceArgs {
+  const int32_t* rowptr;
+  const int32_t* colind;
+  const int32_t* tpos;    // transpose position of every stored entry
+  int32_t n;
+  int32_t phase;          // columns j with dphase[j] == phase contribute
+  const int32_t* dphase;  // per column: the phase whose launch leaves D_j in memory
+  const int32_t* dld;     // per column: leading dimension of D_j
+  const int64_t* doff;    // per column: offset of D_j from base (elements, or bytes when bytes_off)
+  const void* base;
+  int bytes_off;
+  void* ga;               // accumulated in place (zeroed at the start of the call)
+};
+hipError_t launch_adjoint_reduce(const DetReduceArgs& a, int vdtype, int num_cus, hipStream_t s);
 
 // ---- large-order path (large.hip) ----
 struct LargeArgs {
@@ -94,6 +114,8 @@ struct LargeArgs {
   int lds_limit;          // device limit on LDS bytes per workgroup
   int panel_rows;         // reduction: rows of the panel kept in LDS (set by its launcher)
   int panel_off;          // reduction: offset (doubles) of that copy after the row partials
+  int nb;                 // reduction: panel width (even, 2..48)
+  int red_per_cu;         // reduction: workgroups per compute unit its LDS is laid out for (1 or 2)
   void* x;                // forward output (value type vdtype)
   const void* gx;         // backward input
   void* ga;               // backward output (accumulated)
@@ -102,12 +124,13 @@ struct LargeArgs {
   int grid;
   int fp64;               // 1: compute in FP64, 0: FP32
   int only_flagged;       // 1: process only items whose fallback flag is set
+  int det;                // backward: leave D_j (FP64, lower triangle) in the W slab instead of
+                          // scatter-adding it (deterministic assembly afterwards)
 };
 enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
-int reduction_blocks_per_cu();  // workgroups per compute unit the reduction is laid out for
 int back_blocks_per_cu();       // the same for the back-transformation
 int adjoint_blocks_per_cu();    // and for the adjoint
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);
@@ -116,6 +139,10 @@ hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s);
 size_t eig_lds_bytes(int max_m);
 size_t apply_scratch_elems(int ld);  // scratch elements per item of the back-transformation
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
+// the forward's column from the reflectors and Z, without forming Q
+// (one wavefront per submatrix)
+hipError_t launch_column_factored(const LargeArgs& a, hipStream_t s);
+int column_waves_per_cu();
 hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s);
 
 }  // namespace submat

@@ -38,7 +38,10 @@ constexpr int kBackPerCU = 2;
 constexpr int kAdjBlock = 256;
 constexpr int kAdjNW = kAdjBlock / kWave;
 constexpr int kAdjPerCU = 2;
-constexpr int kNB = 16;  // panel width of the reduction (16 measured best of 8..48 at orders ~400)
+// Panel width of the reduction: a launch parameter (LargeArgs::nb, even,
+// 8..kNBMax; the tuning table's default 16 was measured best of 8..48 at
+// orders ~400 with two workgroups per compute unit).
+constexpr int kNBMax = 48;
 
 template <class T> __device__ __forceinline__ T* at(void* base, int64_t off_bytes) {
   return (T*)((char*)base + off_bytes);
@@ -46,6 +49,12 @@ template <class T> __device__ __forceinline__ T* at(void* base, int64_t off_byte
 template <class T> __device__ __forceinline__ const T* at(const void* base, int64_t off_bytes) {
   return (const T*)((const char*)base + off_bytes);
 }
+
+// A column whose order no longer fits the slot and LDS sizes its plan was
+// built for (the caller changed a pattern under a cached plan) is not
+// computed: every kernel skips it, and the output kernels write NaN over its
+// segment and count it.
+__device__ __forceinline__ bool order_mismatch(const LargeArgs& a, int m, int ld) { return m > ld || m > a.max_m; }
 
 __device__ __forceinline__ bool skip_item(const LargeArgs& a, int it) {
   const int fl = a.flags[it];
@@ -71,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
     T* S = at<T>(a.S, a.off[it]);
     for (int i = tid; i < m; i += kBlock) R[i] = a.colind[a0 + i];
     __syncthreads();
@@ -105,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_large(LargeArgs a) {
 // per SIMD): while one item waits on a column's serial steps (norm,
 // reflector, barriers), the other streams its trailing matrix.
 constexpr int kRedNW = 4;
-constexpr int kRedPerCU = 2;  // workgroups per compute unit the LDS budget is shared by
+// workgroups per compute unit the LDS budget is shared by: a template
+// parameter of the kernel (1 or 2, LargeArgs::red_per_cu at launch)
 constexpr int kRedBlock = kRedNW * kWave;
 // y = A v for a symmetric n x n matrix given by its lower triangle (column
 // major, leading dimension ld), v and y in LDS, called by the whole
@@ -148,13 +159,13 @@ __device__ __forceinline__ double wave_strip_sum(double (&x)[kStrip]) {
 // columns, leading dimension ld): z[c] = P[:, c]^T v, with the lane
 // partials and the reduction of the symv's strips.
 // Rows [0, nl) of the panel are read from its LDS copy L (row-major, stride
-// kPanelLd, the panel's column c at L[row * kPanelLd + c]), the rest from
-// global memory.
-constexpr int kPanelLd = kNB + 1;  // odd stride: the lanes of a column read spread over the banks
+// pld = nb + 1, the panel's column c at L[row * pld + c]), the rest from
+// global memory. The odd stride spreads the lanes of a column read over the
+// LDS banks.
 template <class T>
 __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld, int n, int ncol, int c0,
                                                  const double* __restrict__ v, double* z, int lane, int pl,
-                                                 const double* __restrict__ L, int nl) {
+                                                 const double* __restrict__ L, int nl, int pld) {
   double cd[kStrip];
   int col[kStrip];
 #pragma unroll
@@ -168,7 +179,7 @@ __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld
 #pragma unroll
     for (int u = 0; u < kStrip; ++u) {
       const int c = c0 + (u ^ pl);
-      cd[u] = fma(c < ncol ? L[r * kPanelLd + (c < ncol ? c : 0)] : 0.0, vr, cd[u]);
+      cd[u] = fma(c < ncol ? L[r * pld + (c < ncol ? c : 0)] : 0.0, vr, cd[u]);
     }
   }
   for (int r = nl + lane; r - lane < n; r += 2 * kWave) {
@@ -200,7 +211,7 @@ template <class T>
 __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
                                   double* spart, int max_m, const T* __restrict__ Vp, const T* __restrict__ Wp,
                                   int npc, double* z1, double* z2, const double* __restrict__ Vl,
-                                  const double* __restrict__ Wl, int nl) {
+                                  const double* __restrict__ Wl, int nl, int pld) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int pl = strip_perm(lane);
   double* my = spart + (int64_t)wv * max_m;
@@ -214,7 +225,7 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
     if (s < nextra) {
       const bool isw = s < nps;
       panel_strip_dots(isw ? Wp : Vp, ld, n, npc, (isw ? s : s - nps) * kStrip, v, isw ? z1 : z2, lane, pl,
-                       isw ? Wl : Vl, nl);
+                       isw ? Wl : Vl, nl, pld);
       continue;
     }
     const int c0 = (s - nextra) * kStrip;
@@ -359,12 +370,13 @@ __device__ __forceinline__ void panel_correct2(const T* __restrict__ P, const T*
   an += a1;
 }
 
-template <class T>
-__global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeArgs a) {
+template <class T, int PERCU>
+__global__ __launch_bounds__(kRedBlock, PERCU) void k_tridiagonalise(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   __shared__ double red[kRedNW];
-  __shared__ double vk[kNB], wk[kNB], z1[kNB], z2[kNB];
+  __shared__ double vk[kNBMax], wk[kNBMax], z1[kNBMax], z2[kNBMax];
+  const int nb = a.nb, pld = a.nb + 1;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   // LDS: v, then one region holding the symv's per-wave row partials
   // (kRedNW rows of max_m; row 0 becomes y = A22 v, row 1 then the next
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
   // not go back to global memory
   const int pc = a.panel_rows;
   double* Vl = spart + (int64_t)a.panel_off;
-  double* Wl = Vl + (int64_t)pc * kPanelLd;
+  double* Wl = Vl + (int64_t)pc * pld;
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
@@ -387,13 +399,14 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
     T* S = at<T>(a.S, a.off[it]);
     T* Wb = at<T>(a.W, a.off[it]);  // W: column c at Wb + c*ld, rows indexed globally
     T* d = at<T>(a.d, a.doff[it]);
     T* e = at<T>(a.e, a.voff[it]);
     T* tau = at<T>(a.tau, a.voff[it]);
-    for (int k0 = 0; k0 + 2 < m; k0 += kNB) {
-      const int nbt = (m - 2 - k0) < kNB ? (m - 2 - k0) : kNB;
+    for (int k0 = 0; k0 + 2 < m; k0 += nb) {
+      const int nbt = (m - 2 - k0) < nb ? (m - 2 - k0) : nb;
       for (int i = 0; i < nbt; ++i) {
         const int k = k0 + i;
         const int n2 = m - k - 1;
@@ -431,7 +444,7 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
           const double vq = (q == 0) ? 1.0 : xq * scale;
           sv[q] = vq;
           x[q] = (T)vq;
-          if (i + q < pc) Vl[(i + q) * kPanelLd + i] = (double)(T)vq;
+          if (i + q < pc) Vl[(i + q) * pld + i] = (double)(T)vq;
         }
         if (tid == 0) {
           d[k] = (T)dkk;
@@ -446,8 +459,8 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
         // panel dots z1 = W^T v, z2 = V^T v run as extra strips.
         const int nl = pc - i > 0 ? (pc - i < n2 ? pc - i : n2) : 0;  // cached rows of this column
         symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m,
-                          S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2, Vl + i * kPanelLd,
-                          Wl + i * kPanelLd, nl);
+                          S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2, Vl + i * pld,
+                          Wl + i * pld, nl, pld);
         __syncthreads();
         // each thread sums its rows' partials (fixed order), applies
         // y -= V z1 + W z2 and, from the same loads, the next column's
@@ -467,14 +480,14 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
               double nx = (double)S[(int64_t)(k + 1) * ld + (k + 1 + r)];
               if (i > 0) {
                 if (cached)
-                  panel_correct2(Vl + (i + r) * kPanelLd, Wl + (i + r) * kPanelLd, 1, z1, z2, wk, vk, i, acc, nx);
+                  panel_correct2(Vl + (i + r) * pld, Wl + (i + r) * pld, 1, z1, z2, wk, vk, i, acc, nx);
                 else
                   panel_correct2(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, wk, vk, i, acc,
                                  nx);
               }
               an[rr] = nx;
             } else if (i > 0) {
-              acc = cached ? panel_correct(Vl + (i + r) * kPanelLd, Wl + (i + r) * kPanelLd, 1, z1, z2, i, acc)
+              acc = cached ? panel_correct(Vl + (i + r) * pld, Wl + (i + r) * pld, 1, z1, z2, i, acc)
                            : panel_correct(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, i, acc);
             }
             sy[r] = acc;
@@ -493,7 +506,7 @@ __global__ __launch_bounds__(kRedBlock, kRedPerCU) void k_tridiagonalise(LargeAr
           if (r < n2) {
             const double wr = tk * sy[r] - Kc * sv[r];
             Wb[(int64_t)i * ld + (k + 1 + r)] = (T)wr;
-            if (i + r < pc) Wl[(i + r) * kPanelLd + i] = (double)(T)wr;
+            if (i + r < pc) Wl[(i + r) * pld + i] = (double)(T)wr;
             if (fuse_next) sa[r] = an[rr] - sv[r] * w0 - wr;
           }
         }
@@ -774,9 +787,9 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
     T* dg = at<T>(a.d, a.doff[it]);
     const T* eg = at<T>((const void*)a.e, a.voff[it]);
-    T* Y = at<T>(a.S, a.off[it]);
     double* Z = at<double>(a.escr, a.eoff[it]);
     double* U = Z + (int64_t)ld * ld;
     for (int i = tid; i < m; i += kEigBlock) {
@@ -1040,6 +1053,7 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
     T* Qz = at<T>(a.Q, a.qoff[it]);  // Z, column-major, for the back-transformation
     double* Z = at<double>(a.escr, a.eoff[it]);
     // 1/||z|| of each column as left by the eigensolver (row 0 of the U
@@ -1227,6 +1241,7 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_apply_reflectors(Lar
     const int j = a.items[it];
     const int m = a.rowptr[j + 1] - a.rowptr[j];
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
     const T* S = at<T>((const void*)a.S, a.off[it]);
     T* Q = at<T>(a.Q, a.qoff[it]);
     const T* tau = at<T>((const void*)a.tau, a.voff[it]);
@@ -1284,6 +1299,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) {
+      for (int r = tid; r < m; r += kBlock) ((VT*)a.x)[a0 + r] = (VT)NAN;
+      if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_STALE], 1ull);
+      continue;
+    }
     const int c = a.cidx[j];
     const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
@@ -1296,6 +1316,112 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
       for (int q = 0; q < m; ++q) s = fma((double)Q[(int64_t)q * ld + r], wv[q], s);
       x[r] = bad ? (VT)NAN : (VT)s;
     }
+  }
+}
+
+// -------------------------------------------- column from the factors
+// Forward without the eigenvector matrix: with Q = Q1 Z and Q1 = H_0 ...
+// H_{m-3}, the column is
+//   x = Q1 (Z (f(lambda) o (Z^T (Q1^T e_c)))),
+// O(m^2) work per submatrix instead of forming Q (2 m^3). One wavefront per
+// submatrix; lane l holds the vector's rows l, l + 64, ... in registers.
+// Each reflector H_k = I - tau_k v_k v_k^T (v_k in column k of the S slab,
+// zero above row k + 1, 1 at row k + 1, zero below row m) costs one wave
+// reduction; Z^T u takes the columns of Z eight at a time (one coalesced
+// load per column per row group, the strip reduction of the symv), Z y
+// walks the columns of Z with y broadcast from LDS.
+constexpr int kColWavesPerCU = 16;
+
+template <class T, int NPL>
+__device__ __forceinline__ void apply_reflector(const T* __restrict__ v, double tk, int m, int lane, double (&u)[NPL]) {
+  double d = 0.0;
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int r = lane + kWave * i;
+    if (r < m) d = fma((double)v[r], u[i], d);
+  }
+  d = tk * wave_sum(d);
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int r = lane + kWave * i;
+    if (r < m) u[i] = fma(-d, (double)v[r], u[i]);
+  }
+}
+
+template <class T, class VT, int NPL>
+__global__ __launch_bounds__(kWave) void k_column_factored(LargeArgs a) {
+  extern __shared__ double cdyn[];
+  __shared__ int s_item;
+  const int lane = threadIdx.x;
+  const int pl = strip_perm(lane);
+  double* yv = cdyn;  // max_m: f(lambda) o (Z^T Q1^T e_c)
+  for (;;) {
+    const int it = next_item(a.work_ctr, &s_item);
+    if (it >= a.n_items) break;
+    if (skip_item(a, it)) continue;
+    const int fl = a.flags[it];
+    const int j = a.items[it];
+    const int a0 = a.rowptr[j];
+    const int m = a.rowptr[j + 1] - a0;
+    const int ld = a.ldm[it];
+    VT* x = (VT*)a.x + a0;
+    if (order_mismatch(a, m, ld) || m > NPL * kWave) {
+      for (int r = lane; r < m; r += kWave) x[r] = (VT)NAN;
+      if (lane == 0) atomicAdd((unsigned long long*)&a.status[ST_STALE], 1ull);
+      continue;
+    }
+    const int c = a.cidx[j];
+    const T* V = at<T>((const void*)a.S, a.off[it]);
+    const T* Z = at<T>((const void*)a.Q, a.qoff[it]);
+    const T* tau = at<T>((const void*)a.tau, a.voff[it]);
+    const T* lam = at<T>((const void*)a.d, a.doff[it]);
+    const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
+    double u[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) u[i] = (lane + kWave * i == c) ? 1.0 : 0.0;
+    // u = Q1^T e_c = H_{m-3} ... H_0 e_c
+    for (int k = 0; k + 2 < m; ++k) apply_reflector<T, NPL>(V + (int64_t)k * ld, (double)tau[k], m, lane, u);
+    // y = f(lambda) o (Z^T u), eight columns of Z per pass
+    for (int j0 = 0; j0 < m; j0 += kStrip) {
+      double cd[kStrip];
+#pragma unroll
+      for (int s2 = 0; s2 < kStrip; ++s2) cd[s2] = 0.0;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int r = lane + kWave * i;
+        if (r < m) {
+#pragma unroll
+          for (int s2 = 0; s2 < kStrip; ++s2) {
+            const int col = j0 + (s2 ^ pl);
+            cd[s2] = fma(col < m ? (double)Z[(int64_t)col * ld + r] : 0.0, u[i], cd[s2]);
+          }
+        }
+      }
+      const double tot = wave_strip_sum(cd);
+      const int col = j0 + pl;
+      if ((lane & (kWave / kStrip - 1)) == 0 && col < m) yv[col] = spec_f((double)lam[col], a.fn) * tot;
+    }
+    __syncthreads();
+    // u = Z y
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) u[i] = 0.0;
+    for (int jj = 0; jj < m; ++jj) {
+      const double yj = yv[jj];
+      const T* zc = Z + (int64_t)jj * ld;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int r = lane + kWave * i;
+        if (r < m) u[i] = fma((double)zc[r], yj, u[i]);
+      }
+    }
+    // x = Q1 u = H_0 ... H_{m-3} u
+    for (int k = m - 3; k >= 0; --k) apply_reflector<T, NPL>(V + (int64_t)k * ld, (double)tau[k], m, lane, u);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) {
+      const int r = lane + kWave * i;
+      if (r < m) x[r] = bad ? (VT)NAN : (VT)u[i];
+    }
+    __syncthreads();
   }
 }
 
@@ -1323,6 +1449,11 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
     const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) {
+      for (int r = tid; r < m; r += kAdjBlock) atomicAdd(&((VT*)a.ga)[a0 + r], (VT)NAN);
+      if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_STALE], 1ull);
+      continue;
+    }
     const int c = a.cidx[j];
     const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     T* Ms = at<T>(a.S, a.off[it]);
@@ -1358,6 +1489,16 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
     __syncthreads();
     wg_gemm<T, kAdjNW, false, false, false, 1>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
     wg_gemm<T, kAdjNW, false, true, true, 1>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
+    if (a.det) {
+      // deterministic mode: D (lower triangle, FP64) into this item's W slot
+      // (T1 is dead), assembled afterwards in a fixed order
+      double* D64 = at<double>(a.W, a.off[it]);
+      for (int lo = wv; lo < m; lo += kAdjNW)
+        for (int hi = lo + lane; hi < m; hi += kWave)
+          D64[(int64_t)lo * ld + hi] = bad ? (double)NAN : (double)Ms[(int64_t)lo * ld + hi];
+      __syncthreads();
+      continue;
+    }
     VT* ga = (VT*)a.ga;
     for (int k = wv; k < m; k += kAdjNW) {
       const int r = R[k];
@@ -1399,34 +1540,41 @@ hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-int reduction_blocks_per_cu() { return kRedPerCU; }
 int back_blocks_per_cu() { return kBackPerCU; }
 int adjoint_blocks_per_cu() { return kAdjPerCU; }
 
 // static LDS of k_tridiagonalise (block_sum scratch, the next column's
 // coefficients, panel dots) plus a margin
-constexpr size_t kTridiagStaticLds = 2048;
+constexpr size_t kTridiagStaticLds = 4096;
 
-template <class T>
+template <class T, int PERCU>
 static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
   LargeArgs a = a0;
+  const int pld = a.nb + 1;
   const size_t part = vec_lds(a, kRedNW, 8), gemm = gemm_lds_elems<kRedNW>() * sizeof(T);
   const size_t base = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
   // the panel copy takes what is left of the workgroup's share of the LDS
-  // (kRedPerCU workgroups per compute unit), up to the largest order
-  const int64_t left = (int64_t)a.lds_limit / kRedPerCU - (int64_t)base - (int64_t)kTridiagStaticLds;
-  int rows = left > 0 ? (int)(left / (2 * kPanelLd * sizeof(double))) : 0;
+  // (PERCU workgroups per compute unit), up to the largest order
+  const int64_t left = (int64_t)a.lds_limit / PERCU - (int64_t)base - (int64_t)kTridiagStaticLds;
+  int rows = left > 0 ? (int)(left / (2 * pld * sizeof(double))) : 0;
   if (rows > a.max_m) rows = a.max_m;
   a.panel_rows = rows;
   a.panel_off = (int)((part > gemm ? part : gemm) / sizeof(double));
-  const size_t lds = base + (size_t)rows * 2 * kPanelLd * sizeof(double);
-  hipLaunchKernelGGL(k_tridiagonalise<T>, dim3(a.grid), dim3(kRedBlock), lds, s, a);
+  const size_t lds = base + (size_t)rows * 2 * pld * sizeof(double);
+  hipLaunchKernelGGL((k_tridiagonalise<T, PERCU>), dim3(a.grid), dim3(kRedBlock), lds, s, a);
 }
 
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  if (a.fp64) launch_tridiag_t<double>(a, s);
-  else launch_tridiag_t<float>(a, s);
+  if (a.nb < 2 || a.nb > kNBMax || (a.nb & 1) || (a.red_per_cu != 1 && a.red_per_cu != 2))
+    return hipErrorInvalidValue;
+  if (a.fp64) {
+    if (a.red_per_cu == 1) launch_tridiag_t<double, 1>(a, s);
+    else launch_tridiag_t<double, 2>(a, s);
+  } else {
+    if (a.red_per_cu == 1) launch_tridiag_t<float, 1>(a, s);
+    else launch_tridiag_t<float, 2>(a, s);
+  }
   return hipGetLastError();
 }
 
@@ -1468,6 +1616,30 @@ hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s) {
     SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_apply_column<double, VT>), dim3(a.grid), dim3(kBlock), lds, s, a));
   } else {
     SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_apply_column<float, VT>), dim3(a.grid), dim3(kBlock), lds, s, a));
+  }
+  return hipGetLastError();
+}
+
+template <class T, class VT>
+static void dispatch_column_factored(const LargeArgs& a, size_t lds, hipStream_t s) {
+  if (a.max_m <= 8 * kWave)
+    hipLaunchKernelGGL((k_column_factored<T, VT, 8>), dim3(a.grid), dim3(kWave), lds, s, a);
+  else if (a.max_m <= 16 * kWave)
+    hipLaunchKernelGGL((k_column_factored<T, VT, 16>), dim3(a.grid), dim3(kWave), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_column_factored<T, VT, 32>), dim3(a.grid), dim3(kWave), lds, s, a);
+}
+
+int column_waves_per_cu() { return kColWavesPerCU; }
+
+hipError_t launch_column_factored(const LargeArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if (a.max_m > 32 * kWave) return hipErrorInvalidValue;
+  const size_t lds = vec_lds(a, 1, 8);
+  if (a.fp64) {
+    SUBMAT_VT_SWITCH(a.vdtype, (dispatch_column_factored<double, VT>(a, lds, s)));
+  } else {
+    SUBMAT_VT_SWITCH(a.vdtype, (dispatch_column_factored<float, VT>(a, lds, s)));
   }
   return hipGetLastError();
 }

@@ -6,10 +6,10 @@
 //
 // Layout: the working matrix A = S V and V live column-major in LDS
 // (leading dimension MMAX+1). Column pairs are visited in round-robin
-// tournament order, m/2 disjoint pairs per round, and each pair is handled
-// by its two lanes without any reduction across the wavefront. Gram entries
-// and the rotation angle are always computed in FP64, also when the
-// columns are FP32.
+// tournament order, m/2 disjoint pairs per round; each pair is handled by a
+// group of 128/MMAX lanes that split its rows and reduce its Gram sums with
+// DPP lane exchanges. Gram entries and the rotation angle are always
+// computed in FP64, also when the columns are FP32.
 #include <math.h>
 
 #include "common.hpp"
@@ -30,13 +30,6 @@ struct SmallShared {
   int R[MMAX];
   int item;
 };
-
-__device__ __forceinline__ int tournament_partner(int p, int rd, int N) {
-  if (p == N - 1) return rd;
-  if (p == rd) return N - 1;
-  int q = (2 * rd - p) % (N - 1);
-  return q < 0 ? q + (N - 1) : q;
-}
 
 // S[k][l] = A[R[k]][R[l]] (stored pattern, 0 elsewhere), then (S + S^T)/2.
 template <class T, class VT, int MMAX>
@@ -67,16 +60,21 @@ __device__ void gather_small(const int32_t* __restrict__ rowptr, const int32_t* 
 }
 
 // One-sided Jacobi on A = S (columns orthogonalised by right rotations,
-// accumulated in V). Per round the pair (lo, hi) belongs to two lanes: lane
-// lo forms the 2x2 Gram matrix in FP64 and the rotation, hands (c, s) to
-// lane hi by a cross-lane shuffle, then lane lo rotates the two columns of A
-// and lane hi the two columns of V, in place in LDS (no other lane touches
-// them in that round). On return V holds eigenvectors and lam[p] = a_p . v_p
-// the signed eigenvalues. Returns true when a full sweep needed no rotation.
+// accumulated in V). Per round the column pairs of the round-robin
+// tournament are disjoint; pair q of a round belongs to the G = 128 / MMAX
+// lanes q*G .. q*G + G-1, lane r of the group taking rows r, r + G, ...
+// The group forms the pair's 2 x 2 Gram matrix in FP64 (partial sums, then
+// a DPP reduction within the group), every lane of the group derives the
+// same rotation from it, and each lane rotates its own rows of both columns
+// of A and of V, in place in LDS. On return V holds eigenvectors and
+// lam[p] = a_p . v_p the signed eigenvalues. Returns true when a full sweep
+// needed no rotation.
 template <class T, int MMAX>
 __device__ bool jacobi_small(T* A, T* V, int m, double* lam) {
   constexpr int LD = MMAX + 1;
+  constexpr int G = 128 / MMAX;  // lanes per pair: 8, 4 or 2
   const int lane = threadIdx.x;
+  const int pq = lane / G, r0 = lane - pq * G;
   for (int q = lane; q < m * LD; q += kWave) {
     const int c = q / LD, r = q - c * LD;
     V[q] = (r == c) ? T(1) : T(0);
@@ -89,43 +87,46 @@ __device__ bool jacobi_small(T* A, T* V, int m, double* lam) {
   for (int sweep = 0; sweep < 40; ++sweep) {
     int rotated = 0;
     for (int rd = 0; rd < N - 1; ++rd) {
-      const int q = tournament_partner(lane, rd, N);
-      const bool act = lane < m && q < m;
-      const int lo = lane < q ? lane : q;
-      const int hi = lane < q ? q : lane;
-      double cs = 1.0, sn = 0.0;
-      int doit = 0;
-      if (act && lane == lo) {
+      // circle method: pair 0 = (rd, N-1), pair k = (rd + k, rd - k) mod N-1
+      int i1, i2;
+      if (pq == 0) {
+        i1 = rd;
+        i2 = N - 1;
+      } else {
+        i1 = (rd + pq) % (N - 1);
+        i2 = (rd - pq + (N - 1)) % (N - 1);
+      }
+      const int lo = i1 < i2 ? i1 : i2, hi = i1 < i2 ? i2 : i1;
+      const bool act = 2 * pq < N && hi < m;  // the pair exists and is not the odd player's bye
+      double sa = 0.0, sb = 0.0, g = 0.0;
+      if (act) {
         const T* x = A + lo * LD;
         const T* y = A + hi * LD;
-        double sa = 0.0, sb = 0.0, g = 0.0;
-        for (int i = 0; i < m; ++i) {
+        for (int i = r0; i < m; i += G) {
           const double xi = (double)x[i], yi = (double)y[i];
           sa = fma(xi, xi, sa);
           sb = fma(yi, yi, sb);
           g = fma(xi, yi, g);
         }
-        if (g * g > tol2 * sa * sb) {
-          const double zeta = (sb - sa) / (2.0 * g);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          cs = 1.0 / sqrt(1.0 + t * t);
-          sn = cs * t;
-          doit = 1;
-          rotated = 1;
-        }
       }
-      const int src = act ? lo : lane;
-      cs = __shfl(cs, src, kWave);
-      sn = __shfl(sn, src, kWave);
-      doit = __shfl(doit, src, kWave);
-      if (act && doit) {
-        T* X = (lane == lo ? A : V) + lo * LD;
-        T* Y = (lane == lo ? A : V) + hi * LD;
-        const T c = (T)cs, s = (T)sn;
-        for (int i = 0; i < m; ++i) {
-          const T x = X[i], y = Y[i];
-          X[i] = c * x - s * y;
-          Y[i] = s * x + c * y;
+      sa = group_sum<G>(sa);
+      sb = group_sum<G>(sb);
+      g = group_sum<G>(g);
+      if (act && g * g > tol2 * sa * sb) {
+        const double zeta = (sb - sa) / (2.0 * g);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t);
+        const T c = (T)cs, s = (T)(cs * t);
+        rotated = 1;
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          T* X = (w == 0 ? A : V) + lo * LD;
+          T* Y = (w == 0 ? A : V) + hi * LD;
+          for (int i = r0; i < m; i += G) {
+            const T x = X[i], y = Y[i];
+            X[i] = c * x - s * y;
+            Y[i] = s * x + c * y;
+          }
         }
       }
       __syncthreads();
@@ -163,10 +164,13 @@ __device__ void finish_forward(const T* V, SmallShared<MMAX>& sh, int m, int c, 
 // every stored pair (R[k], R[l]) at position q gets ga[q] += D[k][l].
 // The symmetric middle factor Ms is formed in LDS, then D is produced one
 // column at a time (y = Ms V[k, :]^T, D[:, k] = V y) and scattered.
+// With dout (deterministic mode) D is written there, m x m column-major,
+// instead of being scatter-added.
 template <class T, class VT, int MMAX, bool POW>
 __device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c, const SpecFn& fn, bool bad,
                                 const VT* __restrict__ w_seg, VT* __restrict__ ga,
-                                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind) {
+                                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colind,
+                                double* __restrict__ dout) {
   constexpr int LD = MMAX + 1;
   const int lane = threadIdx.x;
   double* Ms = sh.A;  // the working columns are no longer needed
@@ -205,11 +209,15 @@ __device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c,
       sh.dk[lane] = dk;
     }
     __syncthreads();
-    const int r = sh.R[k];
-    const int s0 = rowptr[r], s1 = rowptr[r + 1];
-    for (int q = s0 + lane; q < s1; q += kWave) {
-      const int l = find_sorted(sh.R, m, colind[q]);
-      if (l >= 0) atomicAdd(&ga[q], bad ? (VT)NAN : (VT)sh.dk[l]);
+    if (dout) {
+      for (int l = lane; l < m; l += kWave) dout[(int64_t)k * m + l] = bad ? (double)NAN : sh.dk[l];
+    } else {
+      const int r = sh.R[k];
+      const int s0 = rowptr[r], s1 = rowptr[r + 1];
+      for (int q = s0 + lane; q < s1; q += kWave) {
+        const int l = find_sorted(sh.R, m, colind[q]);
+        if (l >= 0) atomicAdd(&ga[q], bad ? (VT)NAN : (VT)sh.dk[l]);
+      }
     }
     __syncthreads();
   }
@@ -227,6 +235,16 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
     const int j = args.items[it];
     const int a0 = args.rowptr[j];
     const int m = args.rowptr[j + 1] - a0;
+    if (m > MMAX || (BWD && args.dout && m != args.dld[j])) {
+      // the order exceeds what this launch was sized for (the pattern changed
+      // under a cached plan): no computation, NaN over the segment, counted
+      for (int r = lane; r < m; r += kWave) {
+        if (BWD) atomicAdd(&((VT*)args.ga)[a0 + r], (VT)NAN);
+        else ((VT*)args.x)[a0 + r] = (VT)NAN;
+      }
+      if (lane == 0) atomicAdd((unsigned long long*)&args.status[ST_STALE], 1ull);
+      continue;
+    }
     const int c = args.cidx[j];
     if (lane < m) sh.R[lane] = args.colind[a0 + lane];
     __syncthreads();
@@ -242,7 +260,8 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
       if (!flagged) {
         if (BWD)
           finish_backward<float, VT, MMAX, POW>(V, sh, m, c, args.fn, false, (const VT*)args.gx + a0,
-                                           (VT*)args.ga, args.rowptr, args.colind);
+                                           (VT*)args.ga, args.rowptr, args.colind,
+                                           args.dout ? args.dout + args.doff[j] : nullptr);
         else
           finish_forward<float, VT, MMAX>(V, sh, m, c, args.fn, false, (VT*)args.x + a0);
         done = true;
@@ -265,7 +284,8 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
       }
       if (BWD)
         finish_backward<double, VT, MMAX, POW>(V, sh, m, c, args.fn, bad, (const VT*)args.gx + a0,
-                                          (VT*)args.ga, args.rowptr, args.colind);
+                                          (VT*)args.ga, args.rowptr, args.colind,
+                                          args.dout ? args.dout + args.doff[j] : nullptr);
       else
         finish_forward<double, VT, MMAX>(V, sh, m, c, args.fn, bad, (VT*)args.x + a0);
     }

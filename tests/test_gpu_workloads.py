@@ -11,14 +11,16 @@ replay), on sampled outputs the FP64 oracle computes column by column:
 
 Tolerances: FP64 1e-10 (kappa <= 1e4) and 1e-9 at kappa = 1e6 (the
 eigendecomposition's backward error eps * ||S|| moves lambda_min by a
-relative eps * kappa ~ 1e-10); FP32 1e-4 at kappa <= 1e3, and 5e-3 where
-the FP32 pass keeps submatrices up to kappa_max = 1e5 (error ~ kappa u32,
-u32 = 6e-8, capped by the 1e5 threshold at ~6e-3)."""
+relative eps * kappa ~ 1e-10); FP32 1e-4 at kappa <= 1e3 (the stated bar)
+and 1e-5 above (measured 1.2e-6 to 1.4e-6 on these samples: the submatrices
+the FP32 pass keeps have kappa far below its 1e5 threshold, the others are
+redone in FP64); every measured error is printed."""
 import numpy as np
 import pytest
 
 import oracle
-from tests.gpu_util import banner, check_launch_shapes, rel_fro, segments, to_dev
+from tests.gpu_util import (affected_columns, atom_block_entries, banner, check_launch_shapes,
+                            neighbour_atom, oracle_adjoint_parallel, rel_fro, segments, to_dev)
 from workloads import generators as G
 
 pytestmark = pytest.mark.gpu
@@ -69,7 +71,7 @@ def test_mixed_density_workload_full_size(kappa, gpu_lib):
     csr = workload(3, kappa)
     cols = sample_columns(csr, 10, G.BASE_SEED + 300)
     ref = oracle_segments(csr, 2, cols)
-    for precision, tol in (("f64", 1e-10), ("f32_mixed", 1e-4 if kappa <= 1e3 else 5e-3)):
+    for precision, tol in (("f64", 1e-10), ("f32_mixed", 1e-4 if kappa <= 1e3 else 1e-5)):
         banner(f"mixed-density n={csr.n} kappa={kappa:g} {precision}")
         x, st = forward(csr, 2, precision)
         assert np.all(np.isfinite(x)) and st["nonpositive"] == 0 and st["unconverged"] == 0
@@ -81,7 +83,8 @@ def test_mixed_density_workload_full_size(kappa, gpu_lib):
 def test_ill_conditioned_workload_full_size(gpu_lib):
     csr = workload(5)
     cols = sample_columns(csr, 8, G.BASE_SEED + 301)
-    for p, precision, tol in ((2, "f32_mixed", 5e-3), (1, "f64", 1e-9), (3, "f64", 1e-9)):
+    for p, precision, tol in ((2, "f32_mixed", 1e-5), (1, "f32_mixed", 1e-5), (3, "f32_mixed", 1e-5),
+                              (1, "f64", 1e-9), (3, "f64", 1e-9)):
         banner(f"kappa=1e6 n={csr.n} p={p} {precision}")
         x, st = forward(csr, p, precision)
         assert np.all(np.isfinite(x)) and st["nonpositive"] == 0 and st["unconverged"] == 0
@@ -90,26 +93,29 @@ def test_ill_conditioned_workload_full_size(gpu_lib):
         assert err <= tol
 
 
-def test_ill_conditioned_workload_adjoint_sampled_entry(gpu_lib):
+@pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
+def test_ill_conditioned_workload_adjoint_sampled_entries(precision, gpu_lib):
+    """Adjoint at n = 212,992 (eigenvectors recomputed: they would need
+    417 GiB) on 8 stored entries of one atom block against the oracle's sum
+    over every submatrix that holds them. FP64 1e-9 (kappa = 1e6); FP32 with
+    FP64 fallback 1e-4."""
     import torch
     import paper_1710_10899_amd as sm
     csr = workload(5)
     w = G.upstream_gradient(csr, G.BASE_SEED + 105)
-    banner(f"adjoint f64 kappa=1e6 n={csr.n} (recompute)")
+    rng = np.random.default_rng(G.BASE_SEED + 206)
+    a = int(rng.integers(csr.n // 13))
+    picks = atom_block_entries(csr, 13, [(a, neighbour_atom(csr, 13, a, rng))], 8, rng)
+    cols = np.unique(np.concatenate([affected_columns(csr, q) for q in picks]))
+    banner(f"adjoint {precision} kappa=1e6 n={csr.n} (recompute)")
     rp, ci, va = to_dev(csr)
-    ga = sm.invroot_bwd(rp, ci, va, torch.from_numpy(w).cuda(), 2).cpu().numpy()
+    ga = sm.invroot_bwd(rp, ci, va, torch.from_numpy(w).cuda(), 2, precision).cpu().numpy()
     st = sm.query_status()
+    del rp, ci, va
+    torch.cuda.empty_cache()
     print(f"gpu adjoint done, status {st}", flush=True)
     assert np.all(np.isfinite(ga)) and st["unconverged"] == 0
-    rows = np.repeat(np.arange(csr.n), csr.row_sizes())
-    q = int(np.random.default_rng(G.BASE_SEED + 206).choice(csr.nnz))
-    i, k = rows[q], csr.colind[q]
-    ri = csr.colind[csr.rowptr[i]:csr.rowptr[i + 1]]
-    rk = csr.colind[csr.rowptr[k]:csr.rowptr[k + 1]]
-    cols = np.intersect1d(ri, rk)
-    ref = np.zeros(csr.nnz)
-    for c0 in range(0, cols.size, 64):  # the oracle in chunks, printing its progress
-        ref += oracle.adjoint(csr.rowptr, csr.colind, csr.vals, csr.n, 2, w, cols=cols[c0:c0 + 64], check=False)
-        print(f"oracle: {min(c0 + 64, cols.size)} of {cols.size} submatrices", flush=True)
-    print(f"entry {q} ({i},{k}) over {cols.size} submatrices: gpu {ga[q]:.15e} oracle {ref[q]:.15e}", flush=True)
-    assert abs(ga[q] - ref[q]) <= 1e-9 * max(1.0, np.abs(ref).max())
+    ref = oracle_adjoint_parallel(csr, 2, w, cols)[picks]
+    err = rel_fro(ga[picks], ref)
+    print(f"{precision}: {picks.size} entries over {cols.size} submatrices, rel_err {err:.3e}", flush=True)
+    assert err <= (1e-9 if precision == "f64" else 1e-4)

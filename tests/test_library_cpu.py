@@ -49,7 +49,7 @@ def test_binding_covers_header():
 def test_version_strerror_options_without_gpu():
     from paper_1710_10899_amd import _lib
     _lib.load()
-    assert _lib.submat_version() == 120
+    assert _lib.submat_version() == 130
     assert _lib.submat_strerror(-3) == "diagonal entry not stored"
     assert _lib.submat_strerror(0) == "ok"
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_KAPPA_MAX) == 1e5
@@ -120,3 +120,51 @@ def test_tuning_table_option(tmp_path, monkeypatch):
     path.write_text("garbage\n")
     _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_TUNE_FILE) == 0.0
+
+
+def test_deterministic_option_and_release_pattern_without_gpu():
+    from paper_1710_10899_amd import _lib
+    _lib.load()
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_DETERMINISTIC) == 0.0
+    _lib.submat_set_option(_lib.SUBMAT_OPT_DETERMINISTIC, 1)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_DETERMINISTIC) == 1.0
+    _lib.submat_set_option(_lib.SUBMAT_OPT_DETERMINISTIC, 0)
+    with pytest.raises(_lib.SubmatError):
+        _lib.submat_set_option(_lib.SUBMAT_OPT_DETERMINISTIC, 0.5)
+    with pytest.raises(_lib.SubmatError) as e:
+        _lib.submat_release_pattern(None, None, 4, 4)
+    assert e.value.code == _lib.SUBMAT_EINVAL
+
+
+def test_csr_wrapper_keeps_index_copies_and_releases_their_plan(monkeypatch):
+    """matfun_csr converts int64 CSR indices to int32 once per sparse tensor
+    and keeps the copies (fixed addresses) while the tensor lives; when it
+    dies the library's plan for those addresses is dropped, so that a later
+    pattern of the same n and nnz that lands on the same addresses builds a
+    plan of its own instead of meeting the old one."""
+    import gc
+
+    import torch
+
+    from paper_1710_10899_amd import _lib, api
+    released = []
+    monkeypatch.setattr(_lib, "_lib", object())  # looks loaded; no call reaches it
+    monkeypatch.setattr(_lib, "submat_release_pattern", lambda *a: released.append(a))
+    dense = torch.tensor([[2.0, 1.0, 0.0], [1.0, 2.0, 1.0], [0.0, 1.0, 2.0]], dtype=torch.float64)
+    a = dense.to_sparse_csr()
+    assert a.crow_indices().dtype == torch.int64
+    rp, ci = api._csr_index32(a)
+    assert rp.dtype == torch.int32 and ci.dtype == torch.int32
+    assert rp.tolist() == a.crow_indices().tolist() and ci.tolist() == a.col_indices().tolist()
+    rp2, ci2 = api._csr_index32(a)
+    assert rp2 is rp and ci2 is ci  # same tensors, same addresses, same plan
+    key = (rp.data_ptr(), ci.data_ptr(), 3, ci.numel())
+    del rp, ci, rp2, ci2
+    gc.collect()
+    assert released == []
+    del a
+    gc.collect()
+    assert released == [key]
+    b = (dense + torch.eye(3, dtype=torch.float64)).to_sparse_csr()
+    rpb, cib = api._csr_index32(b)
+    assert rpb.tolist() == b.crow_indices().tolist()

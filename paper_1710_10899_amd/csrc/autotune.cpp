@@ -7,7 +7,7 @@
 //          (capped by its LDS use at launch)
 //   3 / 4  panel width of the FP64 / FP32 tridiagonal reduction (even, 2..48)
 //   5 / 6  workgroups per compute unit the FP64 / FP32 reduction is laid
-//          out for (1 or 2: its LDS panel copy takes the rest of the share)
+//          out for (1..4: its LDS panel copy takes the rest of the share)
 // Defaults are the gfx950 measurements on the overlap workloads; a file
 // written by the package's autotune script (environment variable
 // SUBMAT_TUNE_FILE, lines "kind m_hi value") overrides them.
@@ -45,7 +45,7 @@ void load_locked(bool use_file) {
         bool ok = e.m_hi >= 1 && e.fp64 >= 0 && e.fp64 <= 6;
         if (e.fp64 <= 2) ok = ok && e.bpc >= 1 && e.bpc <= 32;
         else if (e.fp64 <= 4) ok = ok && e.bpc >= 2 && e.bpc <= 48 && !(e.bpc & 1);
-        else ok = ok && (e.bpc == 1 || e.bpc == 2);
+        else ok = ok && e.bpc >= 1 && e.bpc <= 4;
         if (ok) t.push_back(e);
       }
       std::fclose(f);

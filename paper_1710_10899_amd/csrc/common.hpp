@@ -96,12 +96,11 @@ __device__ __forceinline__ double dpp_f64(double v) {
 // Sum over aligned groups of G consecutive lanes (G = 1, 2, 4 or 8). Each
 // step adds the partner lane's value; IEEE addition is commutative, so every
 // lane of a group ends with the same bits.
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
-  if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
-  if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
-  if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: the other quad of the 8
+// g must be the same in every lane of the wave (the branches are uniform).
+__device__ __forceinline__ double group_sum(double v, int g) {
+  if (g >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: lane ^ 1
+  if (g >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: lane ^ 2
+  if (g >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror: the other quad of the 8
   return v;
 }
 

@@ -130,6 +130,9 @@ constexpr int kRedBlock = kRedNW * kWave;
 // After a barrier, y = sum over waves of the partials, in a fixed order
 // (deterministic), is formed by the caller.
 constexpr int kStrip = 8;
+// row groups of 64 per strip iteration of the symv, by element type
+template <class T> constexpr int kSymvGroups = 2;
+template <> constexpr int kSymvGroups<float> = 2;
 
 // Column-dot reduction of a strip: 64 lanes each hold kStrip partials. Lane
 // l keeps the strip's columns in slots permuted by u -> u ^ p(l), with
@@ -207,7 +210,7 @@ __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld
 // The strips of the symv of the trailing matrix A (n x n, lower triangle)
 // and, first in the schedule, the strips of the panel dots z1 = Wp^T v and
 // z2 = Vp^T v (npc columns each, n rows, leading dimension ld).
-template <class T>
+template <class T, int RG>
 __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const double* __restrict__ v,
                                   double* spart, int max_m, const T* __restrict__ Vp, const T* __restrict__ Wp,
                                   int npc, double* z1, double* z2, const double* __restrict__ Vl,
@@ -238,52 +241,63 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
       cd[u] = 0.0;
       col[u] = (c < n ? c : c0) * ld;
     }
-    // two groups of 64 rows per iteration: 2 * kStrip loads in flight
-    for (int r = c0 + lane; r - lane < n; r += 2 * kWave) {
-      const int r2 = r + kWave;
-      const bool in = r < n, in2 = r2 < n;
-      // unconditional loads (rows past the end read row 0 of a valid column,
-      // columns past the end read column c0) and masked values: no branch
-      // per load
-      const uint32_t ra = in ? r : 0, rb = in2 ? r2 : 0;
-      double av[kStrip], aw[kStrip];
+    // RG groups of 64 rows per iteration: RG * kStrip loads in flight per
+    // lane (more groups for 4-byte elements, so that the bytes in flight
+    // match the FP64 pass's)
+    for (int r = c0 + lane; r - lane < n; r += RG * kWave) {
+      double av[RG][kStrip];
+      bool in[RG];
 #pragma unroll
-      for (int u = 0; u < kStrip; ++u) {
-        av[u] = (double)A[(uint32_t)col[u] + ra];
-        aw[u] = (double)A[(uint32_t)col[u] + rb];
+      for (int g = 0; g < RG; ++g) {
+        // unconditional loads (rows past the end read row 0 of a valid
+        // column, columns past the end read column c0) and masked values:
+        // no branch per load
+        in[g] = r + g * kWave < n;
+        const uint32_t rg = in[g] ? r + g * kWave : 0;
+#pragma unroll
+        for (int u = 0; u < kStrip; ++u) av[g][u] = (double)A[(uint32_t)col[u] + rg];
       }
 #pragma unroll
-      for (int u = 0; u < kStrip; ++u) {
-        const bool cok = c0 + (u ^ pl) < n;
-        av[u] = (in && cok) ? av[u] : 0.0;
-        aw[u] = (in2 && cok) ? aw[u] : 0.0;
+      for (int g = 0; g < RG; ++g) {
+#pragma unroll
+        for (int u = 0; u < kStrip; ++u) {
+          const bool cok = c0 + (u ^ pl) < n;
+          av[g][u] = (in[g] && cok) ? av[g][u] : 0.0;
+        }
       }
-      const double vr = in ? v[r] : 0.0;
-      const double vr2 = in2 ? v[r2] : 0.0;
-      double racc = 0.0, racc2 = 0.0;
+      double vr[RG], racc[RG];
+#pragma unroll
+      for (int g = 0; g < RG; ++g) {
+        vr[g] = in[g] ? v[r + g * kWave] : 0.0;
+        racc[g] = 0.0;
+      }
       if (r - lane >= c0 + kStrip) {  // the whole first group lies below the diagonal block
 #pragma unroll
         for (int u = 0; u < kStrip; ++u) {
-          racc = fma(av[u], vc[u], racc);
-          cd[u] = fma(av[u], vr, cd[u]);
+          racc[0] = fma(av[0][u], vc[u], racc[0]);
+          cd[u] = fma(av[0][u], vr[0], cd[u]);
         }
       } else {
 #pragma unroll
         for (int u = 0; u < kStrip; ++u) {
           const int c = c0 + (u ^ pl);
-          const double a_ = (r >= c) ? av[u] : 0.0;
-          racc = fma(a_, vc[u], racc);
-          cd[u] = fma((r > c) ? a_ : 0.0, vr, cd[u]);
+          const double a_ = (r >= c) ? av[0][u] : 0.0;
+          racc[0] = fma(a_, vc[u], racc[0]);
+          cd[u] = fma((r > c) ? a_ : 0.0, vr[0], cd[u]);
         }
       }
-      // the second group starts 64 rows lower, below the diagonal block
+      // the other groups start 64 rows lower or more, below the diagonal block
 #pragma unroll
-      for (int u = 0; u < kStrip; ++u) {
-        racc2 = fma(aw[u], vc[u], racc2);
-        cd[u] = fma(aw[u], vr2, cd[u]);
+      for (int g = 1; g < RG; ++g) {
+#pragma unroll
+        for (int u = 0; u < kStrip; ++u) {
+          racc[g] = fma(av[g][u], vc[u], racc[g]);
+          cd[u] = fma(av[g][u], vr[g], cd[u]);
+        }
       }
-      if (in) my[r] += racc;
-      if (in2) my[r2] += racc2;
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+        if (in[g]) my[r + g * kWave] += racc[g];
     }
     const double tot = wave_strip_sum(cd);
     if ((lane & (kWave / kStrip - 1)) == 0 && c0 + pl < n) my[c0 + pl] += tot;
@@ -458,7 +472,7 @@ __global__ __launch_bounds__(kRedBlock, PERCU) void k_tridiagonalise(LargeArgs a
         // serves both y[r] += A[r][c] v[c] and y[c] += A[r][c] v[r]; the
         // panel dots z1 = W^T v, z2 = V^T v run as extra strips.
         const int nl = pc - i > 0 ? (pc - i < n2 ? pc - i : n2) : 0;  // cached rows of this column
-        symv_lower_strips(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m,
+        symv_lower_strips<T, kSymvGroups<T>>(S + (int64_t)(k + 1) * ld + (k + 1), ld, n2, sv, spart, a.max_m,
                           S + (int64_t)k0 * ld + (k + 1), Wb + (k + 1), i, z1, z2, Vl + i * pld,
                           Wl + i * pld, nl, pld);
         __syncthreads();
@@ -623,29 +637,120 @@ __device__ __forceinline__ int sturm_count_all(const double* d, const double* e2
   return cnt;
 }
 
-// The count of sturm_count_all together with the logarithmic derivative
-// sd = sum_i q_i'/q_i = d/dx log det(T - xI) = -sum_l 1/(lambda_l - x),
-// from q_i' = -1 + e_{i-1}^2 q_{i-1}' / q_{i-1}^2 (a Newton step for an
-// eigenvalue is -1/sd). The pivots are those of sturm_count_all. Guarded
-// pivots or overflow make sd infinite or NaN, which the caller rejects.
-__device__ __forceinline__ int sturm_newton_all(const double* d, const double* e2, int m, double x, double pivmin,
-                                                double& sd) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int cnt = (int)((uint32_t)__double2hiint(q) >> 31);
-  double qp = -1.0, s = 0.0;
-#pragma unroll 4
+// The count of sturm_count_all at two points x1, x2 in one pass over T (the
+// two recurrences are independent, so their latencies overlap), each with
+// the logarithmic derivative sd = sum_i q_i'/q_i = d/dx log det(T - xI) =
+// -sum_l 1/(lambda_l - x), from q_i' = -1 + e_{i-1}^2 q_{i-1}' / q_{i-1}^2
+// (a Newton step for an eigenvalue is -1/sd). The pivots are those of
+// sturm_count_all. Guarded pivots or overflow make sd infinite or NaN,
+// which the caller rejects.
+__device__ __forceinline__ void sturm_newton_all2(const double* d, const double* e2, int m, double x1, double x2,
+                                                  double pivmin, int& c1, int& c2, double& sd1, double& sd2) {
+  double q1 = d[0] - x1, q2 = d[0] - x2;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  if (fabs(q2) < pivmin) q2 = -pivmin;
+  int n1 = (int)((uint32_t)__double2hiint(q1) >> 31), n2 = (int)((uint32_t)__double2hiint(q2) >> 31);
+  double qp1 = -1.0, qp2 = -1.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 2
   for (int i = 1; i < m; ++i) {
-    const double r = recip(q);
-    s = fma(qp, r, s);
-    const double t = e2[i - 1] * r;
-    qp = fma(t * r, qp, -1.0);
-    q = fma(-e2[i - 1], r, d[i] - x);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += (int)((uint32_t)__double2hiint(q) >> 31);
+    const double ee = e2[i - 1], di = d[i];
+    const double r1 = recip(q1), r2 = recip(q2);
+    s1 = fma(qp1, r1, s1);
+    s2 = fma(qp2, r2, s2);
+    const double t1 = ee * r1, t2 = ee * r2;
+    qp1 = fma(t1 * r1, qp1, -1.0);
+    qp2 = fma(t2 * r2, qp2, -1.0);
+    q1 = fma(-ee, r1, di - x1);
+    q2 = fma(-ee, r2, di - x2);
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    if (fabs(q2) < pivmin) q2 = -pivmin;
+    n1 += (int)((uint32_t)__double2hiint(q1) >> 31);
+    n2 += (int)((uint32_t)__double2hiint(q2) >> 31);
   }
-  sd = fma(qp, recip(q), s);
-  return cnt;
+  sd1 = fma(qp1, recip(q1), s1);
+  sd2 = fma(qp2, recip(q2), s2);
+  c1 = n1;
+  c2 = n2;
+}
+
+// Sturm-safeguarded Newton search for eigenvalue k of an unsplit T: the
+// bracket [lo, hi] (counts clo <= k < chi) is kept exactly as in bisection
+// and the search ends on the same width test; only the next trial point
+// differs. While the bracket holds more than eigenvalue k, it is the
+// midpoint. Once it holds k alone, it is the Newton point x - 1/sd if that
+// lies inside and the Newton steps at least halve every two iterations.
+// Newton from one side never closes the far end, so when the step is within
+// the tolerance, the trial point goes across the eigenvalue towards the open
+// end by (|step| + g) 2^j, j counting such probes.
+struct EigSearch {
+  double lo, hi, x, w1, w2;
+  int clo, chi, k, npr;
+  bool done;
+};
+
+__device__ __forceinline__ bool search_stop(const EigSearch& S, double atol) {
+  return S.hi - S.lo <= 4.0 * kUnitRoundoff * fmax(fabs(S.lo), fabs(S.hi)) + atol || !(S.x > S.lo && S.x < S.hi);
+}
+
+// Start from the multisection counts msc[0..nm) at glo + (i + 1) hstep: the
+// last point with count <= k, and the next one.
+__device__ __forceinline__ void search_init(EigSearch& S, int k, const int* msc, double glo, double ghi, double hstep,
+                                            int m, double atol) {
+  constexpr int nm = kEigBlock;
+  int a2 = 0, b2 = nm;
+  while (a2 < b2) {
+    const int mid = (a2 + b2) >> 1;
+    if (msc[mid] <= k) a2 = mid + 1;
+    else b2 = mid;
+  }
+  // points 0..a2-1 have count <= k, point a2 (if any) has count > k
+  S.lo = a2 > 0 ? glo + a2 * hstep : glo;
+  S.hi = a2 < nm ? glo + (a2 + 1) * hstep : ghi;
+  S.clo = a2 > 0 ? msc[a2 - 1] : 0;
+  S.chi = a2 < nm ? msc[a2] : m;
+  S.x = 0.5 * (S.lo + S.hi);
+  S.w1 = S.w2 = INFINITY;
+  S.npr = 0;
+  S.k = k;
+  S.done = search_stop(S, atol);
+}
+
+__device__ __forceinline__ void search_update(EigSearch& S, int cnt, double sd, double atol) {
+  const bool up = cnt > S.k;
+  if (up) {
+    S.hi = S.x;
+    S.chi = cnt;
+  } else {
+    S.lo = S.x;
+    S.clo = cnt;
+  }
+  const double g = 2.0 * kUnitRoundoff * fmax(fabs(S.lo), fabs(S.hi)) + 0.5 * atol;
+  const double step = -1.0 / sd;
+  const double st = fabs(step);
+  const bool iso = S.chi - S.clo == 1;
+  const double xb = 0.5 * (S.lo + S.hi);
+  double xn = xb, wn = fabs(xb - S.x);
+  if (iso && !(st > 2.0 * g)) {
+    const double pr = S.x + (up ? -1.0 : 1.0) * (st + g) * ldexp(1.0, S.npr);
+    if (pr > S.lo && pr < S.hi) {
+      xn = pr;
+      wn = S.w1;
+      ++S.npr;
+    } else {
+      S.npr = 0;
+    }
+  } else {
+    S.npr = 0;
+    const double xt = S.x + step;
+    if (iso && xt > S.lo && xt < S.hi && !(st > 0.5 * S.w2)) {
+      xn = xt;
+      wn = st;
+    }
+  }
+  S.w2 = S.w1;
+  S.w1 = wn;
+  S.x = xn;
+  S.done = search_stop(S, atol);
 }
 
 __device__ __forceinline__ double guard_pivot(double D, double tol) {
@@ -859,72 +964,34 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
     const double hstep = (ghi - glo) / (kEigBlock + 1);
     if (one_block) msc[tid] = sturm_count_all(d, e2, m, glo + (tid + 1) * hstep, pivmin);
     __syncthreads();
-    for (int jj = tid; jj < m; jj += kEigBlock) {
-      const int s = bs[jj], t = be[jj], k = jj - s;
-      double lo = glo, hi = ghi;
-      if (one_block) {
-        // the last point with count <= k, and the next one
-        int a2 = 0, b2 = kEigBlock;  // counts at points a2-1 (glo for 0) ... search over msc
-        while (a2 < b2) {
-          const int mid = (a2 + b2) >> 1;
-          if (msc[mid] <= k) a2 = mid + 1;
-          else b2 = mid;
+    if (one_block) {
+      // a lane searches eigenvalues jj and jj + kEigBlock together: their
+      // Sturm chains are interleaved in one pass over T (two independent
+      // dependency chains, the d / e^2 loads shared)
+      for (int jj = tid; jj < m; jj += 2 * kEigBlock) {
+        const int j2 = jj + kEigBlock;
+        EigSearch S1, S2;
+        search_init(S1, jj, msc, glo, ghi, hstep, m, atol);
+        if (j2 < m) {
+          search_init(S2, j2, msc, glo, ghi, hstep, m, atol);
+        } else {
+          S2 = S1;
+          S2.done = true;
         }
-        // points 0..a2-1 have count <= k, point a2 (if any) has count > k
-        lo = a2 > 0 ? glo + a2 * hstep : glo;
-        hi = a2 < kEigBlock ? glo + (a2 + 1) * hstep : ghi;
-        int clo = a2 > 0 ? msc[a2 - 1] : 0, chi = a2 < kEigBlock ? msc[a2] : m;
-        // Sturm-safeguarded Newton: the bracket [lo, hi] (counts clo <= k <
-        // chi) is kept exactly as in bisection and the loop ends on the same
-        // width test; only the next trial point differs. While the bracket
-        // holds more than eigenvalue k, it is the midpoint. Once it holds k
-        // alone, it is the Newton point x - 1/sd if that lies inside and the
-        // Newton steps at least halve every two iterations. Newton from one
-        // side never closes the far end, so when the step is within the
-        // tolerance, the trial point goes across the eigenvalue towards the
-        // open end by (|step| + g) 2^j, j counting such probes.
-        double x = 0.5 * (lo + hi), w1 = INFINITY, w2 = INFINITY;
-        int npr = 0;
-        for (int iter = 0; iter < 256; ++iter) {
-          if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(x > lo && x < hi)) break;
-          double sd;
-          const int cnt = sturm_newton_all(d, e2, m, x, pivmin, sd);
-          const bool up = cnt > k;
-          if (up) {
-            hi = x;
-            chi = cnt;
-          } else {
-            lo = x;
-            clo = cnt;
-          }
-          const double g = 2.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + 0.5 * atol;
-          const double step = -1.0 / sd;
-          const double st = fabs(step);
-          const bool iso = chi - clo == 1;
-          const double xb = 0.5 * (lo + hi);
-          double xn = xb, wn = fabs(xb - x);
-          if (iso && !(st > 2.0 * g)) {
-            const double pr = x + (up ? -1.0 : 1.0) * (st + g) * ldexp(1.0, npr);
-            if (pr > lo && pr < hi) {
-              xn = pr;
-              wn = w1;
-              ++npr;
-            } else {
-              npr = 0;
-            }
-          } else {
-            npr = 0;
-            const double xt = x + step;
-            if (iso && xt > lo && xt < hi && !(st > 0.5 * w2)) {
-              xn = xt;
-              wn = st;
-            }
-          }
-          w2 = w1;
-          w1 = wn;
-          x = xn;
+        for (int iter = 0; iter < 256 && !(S1.done && S2.done); ++iter) {
+          int c1, c2;
+          double sd1, sd2;
+          sturm_newton_all2(d, e2, m, S1.x, S2.done ? S1.x : S2.x, pivmin, c1, c2, sd1, sd2);
+          if (!S1.done) search_update(S1, c1, sd1, atol);
+          if (!S2.done) search_update(S2, c2, sd2, atol);
         }
-      } else {
+        lam[jj] = 0.5 * (S1.lo + S1.hi);
+        if (j2 < m) lam[j2] = 0.5 * (S2.lo + S2.hi);
+      }
+    } else {
+      for (int jj = tid; jj < m; jj += kEigBlock) {
+        const int s = bs[jj], t = be[jj], k = jj - s;
+        double lo = glo, hi = ghi;
         for (int iter = 0; iter < 256; ++iter) {
           const double mid = 0.5 * (lo + hi);
           if (hi - lo <= 4.0 * kUnitRoundoff * fmax(fabs(lo), fabs(hi)) + atol || !(mid > lo && mid < hi)) break;
@@ -932,8 +999,8 @@ __global__ __launch_bounds__(kEigBlock) void k_tridiag_eig(LargeArgs a) {
           if (cnt > k) hi = mid;
           else lo = mid;
         }
+        lam[jj] = 0.5 * (lo + hi);
       }
-      lam[jj] = 0.5 * (lo + hi);
     }
     __syncthreads();
     // eigenvectors
@@ -1566,14 +1633,21 @@ static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
 
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  if (a.nb < 2 || a.nb > kNBMax || (a.nb & 1) || (a.red_per_cu != 1 && a.red_per_cu != 2))
-    return hipErrorInvalidValue;
+  if (a.nb < 2 || a.nb > kNBMax || (a.nb & 1) || a.red_per_cu < 1 || a.red_per_cu > 4) return hipErrorInvalidValue;
   if (a.fp64) {
-    if (a.red_per_cu == 1) launch_tridiag_t<double, 1>(a, s);
-    else launch_tridiag_t<double, 2>(a, s);
+    switch (a.red_per_cu) {
+      case 1: launch_tridiag_t<double, 1>(a, s); break;
+      case 2: launch_tridiag_t<double, 2>(a, s); break;
+      case 3: launch_tridiag_t<double, 3>(a, s); break;
+      default: launch_tridiag_t<double, 4>(a, s); break;
+    }
   } else {
-    if (a.red_per_cu == 1) launch_tridiag_t<float, 1>(a, s);
-    else launch_tridiag_t<float, 2>(a, s);
+    switch (a.red_per_cu) {
+      case 1: launch_tridiag_t<float, 1>(a, s); break;
+      case 2: launch_tridiag_t<float, 2>(a, s); break;
+      case 3: launch_tridiag_t<float, 3>(a, s); break;
+      default: launch_tridiag_t<float, 4>(a, s); break;
+    }
   }
   return hipGetLastError();
 }

@@ -61,8 +61,10 @@ __device__ void gather_small(const int32_t* __restrict__ rowptr, const int32_t* 
 
 // One-sided Jacobi on A = S (columns orthogonalised by right rotations,
 // accumulated in V). Per round the column pairs of the round-robin
-// tournament are disjoint; pair q of a round belongs to the G = 128 / MMAX
-// lanes q*G .. q*G + G-1, lane r of the group taking rows r, r + G, ...
+// tournament are disjoint; pair q of a round belongs to the G lanes
+// q*G .. q*G + G-1 (G = 8, 4 or 2 for m <= 16, 32, 64: a function of m
+// alone, so a submatrix gets the same bits whatever launch it is in), lane r
+// of the group taking rows r, r + G, ...
 // The group forms the pair's 2 x 2 Gram matrix in FP64 (partial sums, then
 // a DPP reduction within the group), every lane of the group derives the
 // same rotation from it, and each lane rotates its own rows of both columns
@@ -72,7 +74,7 @@ __device__ void gather_small(const int32_t* __restrict__ rowptr, const int32_t* 
 template <class T, int MMAX>
 __device__ bool jacobi_small(T* A, T* V, int m, double* lam) {
   constexpr int LD = MMAX + 1;
-  constexpr int G = 128 / MMAX;  // lanes per pair: 8, 4 or 2
+  const int G = m <= 16 ? 8 : (m <= 32 ? 4 : 2);  // lanes per pair
   const int lane = threadIdx.x;
   const int pq = lane / G, r0 = lane - pq * G;
   for (int q = lane; q < m * LD; q += kWave) {
@@ -109,9 +111,9 @@ __device__ bool jacobi_small(T* A, T* V, int m, double* lam) {
           g = fma(xi, yi, g);
         }
       }
-      sa = group_sum<G>(sa);
-      sb = group_sum<G>(sb);
-      g = group_sum<G>(g);
+      sa = group_sum(sa, G);
+      sb = group_sum(sb, G);
+      g = group_sum(g, G);
       if (act && g * g > tol2 * sa * sb) {
         const double zeta = (sb - sa) / (2.0 * g);
         const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));

@@ -183,6 +183,32 @@ int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void*
                        int32_t n, int64_t nnz, int32_t p, int32_t dtype, int32_t precision,
                        const void* grad_x, void* grad_a, const void* saved, void* stream);
 
+/*
+ * The forward of submat_invroot_fwd for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): it calls no hipMalloc/hipFree and no allocating
+ * library routine, builds no cached plan and synchronises nothing. Its only
+ * device memory besides the caller's arrays is a fixed scratch array of
+ * 8 MiB + 1 KiB per device, held until the process ends (status slots,
+ * validation bits, a work counter, m_j and c_j).
+ *   Limits: n <= 1048576 (else SUBMAT_ETOOBIG, synchronously); every column
+ *   is taken by the one-wavefront Jacobi path, so orders m_j <= 64 (a longer
+ *   column's segment is NaN and counted in status slot 4, as for a changed
+ *   pattern); precision SUBMAT_PREC_F64 or SUBMAT_PREC_F32_MIXED (else
+ *   SUBMAT_EINVAL). Arguments as for submat_invroot_fwd, without `saved`.
+ *   The pattern is validated on the device within the call: an invalid one
+ *   writes nothing and is counted in status slot 5 (submat_query_counters),
+ *   not reported synchronously.
+ *   Calls on one device share the scratch array: calls that overlap in time
+ *   on the same device (different streams, or threads) race and must be
+ *   serialised; each call clears the counters it uses. submat_query_status /
+ *   submat_query_counters on the call's stream report its counters until the
+ *   next call on that stream.
+ */
+int submat_invroot_fwd_noalloc(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n,
+                               int64_t nnz, int32_t p, int32_t dtype, int32_t precision, void* x_vals,
+                               void* stream);
+
 /* Bytes of the optional `saved` buffer for this pattern and dtype; < 0 on error.
    Builds (and caches) the plan if needed (synchronous). */
 int64_t submat_saved_bytes(const int32_t* rowptr, const int32_t* colind, int32_t n,
@@ -203,7 +229,9 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
  * submatrices, [1] FP64 redos, [2] unconverged, [3] eigenvectors of the
  * tridiagonal eigensolver (large-order path) computed by inverse iteration
  * because their eigenvalue lies in a cluster, [4] columns not computed because
- * their order does not fit the cached plan (the pattern changed under it).
+ * their order does not fit the cached plan (the pattern changed under it) or
+ * exceeds 64 in submat_invroot_fwd_noalloc, [5] calls of
+ * submat_invroot_fwd_noalloc whose pattern failed validation.
  * Returns SUBMAT_EINVAL for n outside 1..8 or out NULL.
  */
 int submat_query_counters(void* stream, int64_t* out, int32_t n);

@@ -58,6 +58,7 @@ SIGNATURES = {
     "submat_matfun_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _D, _I32, _I32, _P, _P, _P, _P]),
     "submat_invroot_fwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P]),
     "submat_invroot_bwd": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P, _P, _P]),
+    "submat_invroot_fwd_noalloc": (ctypes.c_int, [_P, _P, _P, _I32, _I64, _I32, _I32, _I32, _P, _P]),
     "submat_saved_bytes": (_I64, [_P, _P, _I32, _I64, _I32, _I32]),
     "submat_query_status": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "submat_query_counters": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _I32]),
@@ -132,6 +133,11 @@ def submat_matfun_bwd(rowptr, colind, vals, n, nnz, fn, param, dtype, precision,
 def submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream) -> None:
     _check(load().submat_invroot_fwd(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, saved, stream),
            "submat_invroot_fwd")
+
+
+def submat_invroot_fwd_noalloc(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, stream) -> None:
+    _check(load().submat_invroot_fwd_noalloc(rowptr, colind, vals, n, nnz, p, dtype, precision, x_vals, stream),
+           "submat_invroot_fwd_noalloc")
 
 
 def submat_invroot_bwd(rowptr, colind, vals, n, nnz, p, dtype, precision, grad_x, grad_a, saved, stream) -> None:

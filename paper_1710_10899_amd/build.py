@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libsubmat.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["plan.hip", "small.hip", "large.hip", "krylov.hip", "adjoint_reduce.hip", "api.cpp", "autotune.cpp"]
+SOURCES = ["plan.hip", "small.hip", "large.hip", "krylov.hip", "adjoint_reduce.hip", "noalloc.hip", "api.cpp", "autotune.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

@@ -73,6 +73,10 @@ struct DeviceCtx {
 };
 std::map<int, std::unique_ptr<DeviceCtx>> g_dev;
 
+// Streams whose last call was the forward that allocates nothing: its
+// status slots are in that entry point's scratch (device, stream -> address).
+std::map<std::pair<int, uintptr_t>, int64_t*> g_noalloc_status;
+
 // Status block of `stream` on this device, allocated (and zeroed) on first use.
 int stream_status(DeviceCtx* ctx, hipStream_t stream, int64_t** out) {
   auto& slot = ctx->status[(uintptr_t)stream];
@@ -85,6 +89,19 @@ int stream_status(DeviceCtx* ctx, hipStream_t stream, int64_t** out) {
   }
   *out = slot->p;
   return SUBMAT_OK;
+}
+
+int get_ctx(DeviceCtx** out);
+
+// The status block a query on `stream` reads: the no-alloc entry point's
+// scratch when that was the stream's last call, else the stream's own.
+int status_for_query(DeviceCtx* ctx, hipStream_t stream, int64_t** out) {
+  auto it = g_noalloc_status.find({ctx->device, (uintptr_t)stream});
+  if (it != g_noalloc_status.end()) {
+    *out = it->second;
+    return SUBMAT_OK;
+  }
+  return stream_status(ctx, stream, out);
 }
 
 int get_ctx(DeviceCtx** out) {
@@ -863,6 +880,7 @@ int run_call(const int32_t* rowptr, const int32_t* colind, int32_t n, int64_t nn
   if (c.bwd && c.det && W->dsmall.n < (size_t)P->small_d_elems) SEQ_TRY(W->dsmall.alloc(P->small_d_elems));
   int64_t* status = nullptr;
   SEQ_TRY(stream_status(ctx, s, &status));
+  g_noalloc_status.erase({ctx->device, (uintptr_t)s});
   int rc;
   if (timer) {
     timer->s = s;
@@ -1151,6 +1169,27 @@ int submat_invroot_fwd(const int32_t* rowptr, const int32_t* colind, const void*
                            saved, stream);
 }
 
+int submat_invroot_fwd_noalloc(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n,
+                               int64_t nnz, int32_t p, int32_t dtype, int32_t precision, void* x_vals,
+                               void* stream) {
+  SpecFn f{};
+  int rc = check_args(rowptr, colind, vals, n, nnz, dtype, precision);
+  if (!rc) rc = make_fn(SUBMAT_FN_INV_ROOT, (double)p, &f);
+  if (rc) return rc;
+  if (!x_vals || precision == SUBMAT_PREC_F64_PLAIN) return SUBMAT_EINVAL;
+  if (n > kNoAllocMaxN) return SUBMAT_ETOOBIG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DeviceCtx* ctx = nullptr;
+  SEQ_TRY(get_ctx(&ctx));
+  hipStream_t s = (hipStream_t)stream;
+  int64_t* status = nullptr;
+  rc = noalloc_forward(rowptr, colind, vals, n, nnz, f, dtype, precision == SUBMAT_PREC_F32_MIXED, g_opt.kappa_max,
+                       x_vals, ctx->num_cus, s, &status);
+  if (rc) return rc;
+  g_noalloc_status[{ctx->device, (uintptr_t)s}] = status;
+  return SUBMAT_OK;
+}
+
 int submat_invroot_bwd(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                        int32_t p, int32_t dtype, int32_t precision, const void* grad_x, void* grad_a,
                        const void* saved, void* stream) {
@@ -1179,7 +1218,7 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
   int rc = get_ctx(&ctx);
   if (rc) return rc;
   int64_t* st = nullptr;
-  if ((rc = stream_status(ctx, (hipStream_t)stream, &st))) return rc;
+  if ((rc = status_for_query(ctx, (hipStream_t)stream, &st))) return rc;
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   int64_t h[ST_NSLOTS] = {0};
   HIP_TRY(hipMemcpy(h, st, sizeof(h), hipMemcpyDeviceToHost));
@@ -1196,7 +1235,7 @@ int submat_query_counters(void* stream, int64_t* out, int32_t n) {
   int rc = get_ctx(&ctx);
   if (rc) return rc;
   int64_t* st = nullptr;
-  if ((rc = stream_status(ctx, (hipStream_t)stream, &st))) return rc;
+  if ((rc = status_for_query(ctx, (hipStream_t)stream, &st))) return rc;
   HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   HIP_TRY(hipMemcpy(out, st, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost));
   return SUBMAT_OK;

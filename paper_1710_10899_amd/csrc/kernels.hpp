@@ -13,6 +13,7 @@ enum StatusSlot : int {
   ST_UNCONV = 2,      // eigensolver did not converge
   ST_INVITER = 3,     // eigenvectors computed by inverse iteration (eigenvalue clusters)
   ST_STALE = 4,       // columns whose order exceeds what the plan was built for (NaN output)
+  ST_PATTERN = 5,     // calls whose pattern failed device-side validation (no output written)
   ST_NSLOTS = 64,
 };
 
@@ -62,8 +63,18 @@ struct SmallArgs {
   double* dout;          // backward, deterministic: D_j is written here (m x m, column-major)
   const int64_t* doff;   //   at dout + doff[j] instead of being scatter-added,
   const int32_t* dld;    //   in a slot planned for order dld[j]
+  const uint32_t* pattern_err;  // device-side pattern validation bits of this call (nullptr: validated
+                                // at plan build); nonzero: the launch writes nothing
 };
 hipError_t launch_small(const SmallArgs& a, hipStream_t s);
+
+// ---- forward without allocation (noalloc.hip) ----
+// Largest n of the entry point that allocates nothing, and its per-device
+// scratch: status slots, the pattern error word, a work counter, m_j, c_j.
+constexpr int32_t kNoAllocMaxN = 1 << 20;
+int noalloc_forward(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
+                    SpecFn fn, int32_t vdtype, int mixed, double kappa_max, void* x, int num_cus, hipStream_t s,
+                    int64_t** status_out);
 
 // ---- deterministic adjoint assembly (adjoint_reduce.hip) ----
 struct DetReduceArgs {

@@ -231,10 +231,16 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
   __shared__ SmallShared<MMAX> sh;
   const VT* vals = (const VT*)args.vals;
   const int lane = threadIdx.x;
+  if (args.pattern_err && *args.pattern_err) {
+    // the pattern failed the device-side validation of this call: nothing
+    // is written (its segment bounds cannot be trusted), one count
+    if (blockIdx.x == 0 && lane == 0) atomicAdd((unsigned long long*)&args.status[ST_PATTERN], 1ull);
+    return;
+  }
   for (;;) {
     const int it = next_item(args.work_ctr, &sh.item);
     if (it >= args.n_items) break;
-    const int j = args.items[it];
+    const int j = args.items ? args.items[it] : it;
     const int a0 = args.rowptr[j];
     const int m = args.rowptr[j + 1] - a0;
     if (m > MMAX || (BWD && args.dout && m != args.dld[j])) {

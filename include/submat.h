@@ -231,7 +231,9 @@ int submat_query_status(void* stream, int64_t* n_nonpositive, int64_t* n_fallbac
  * because their eigenvalue lies in a cluster, [4] columns not computed because
  * their order does not fit the cached plan (the pattern changed under it) or
  * exceeds 64 in submat_invroot_fwd_noalloc, [5] calls of
- * submat_invroot_fwd_noalloc whose pattern failed validation.
+ * submat_invroot_fwd_noalloc whose pattern failed validation, [6] columns whose
+ * output was written (n after a complete call: every column exactly once,
+ * whichever size bucket, chunk or precision pass took it).
  * Returns SUBMAT_EINVAL for n outside 1..8 or out NULL.
  */
 int submat_query_counters(void* stream, int64_t* out, int32_t n);

@@ -31,9 +31,9 @@ import time
 DEFAULTS = [(1, 128, 8), (1, 256, 4), (1, 1024, 2), (1, 1 << 30, 1),
             (0, 128, 8), (0, 256, 4), (0, 1024, 2), (0, 1 << 30, 1),
             (2, 256, 8), (2, 512, 6), (2, 1024, 4), (2, 1 << 30, 1),
-            (3, 1 << 30, 16), (4, 1 << 30, 16), (5, 1 << 30, 2), (6, 1 << 30, 2)]
+            (3, 1 << 30, 16), (4, 1 << 30, 16), (5, 1 << 30, 2), (6, 1 << 30, 3)]
 # reduction candidates: (panel width, workgroups per compute unit)
-REDUCTION_CANDIDATES = ((8, 2), (16, 2), (24, 2), (32, 2), (16, 1), (24, 1), (32, 1), (48, 1))
+REDUCTION_CANDIDATES = ((8, 2), (16, 2), (24, 2), (32, 2), (16, 1), (32, 1), (16, 3), (24, 3), (16, 4))
 BUCKETS = (128, 256, 512, 1024)
 DENSE_PHASES = ("gather", "tridiagonalise", "back-transform", "apply-column", "adjoint")
 EIG_PHASES = ("tridiagonal-eig", "reorthogonalise")
@@ -125,7 +125,7 @@ def main(argv=None):
                       + f" -> {bpc}", flush=True)
             for kn, kc, precision in ((3, 5, "f64"), (4, 6, "f32_mixed")):
                 res = {}
-                for nb, pc in (REDUCTION_CANDIDATES if not args.quick else ((16, 2), (24, 1), (32, 1))):
+                for nb, pc in (REDUCTION_CANDIDATES if not args.quick else ((16, 2), (16, 3), (24, 2))):
                     write_table(tmp, table_with(table_with(table, kn, bucket, nb), kc, bucket, pc))
                     _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
                     res[(nb, pc)] = time_phases(csr, precision, ("tridiagonalise",), args.reps)

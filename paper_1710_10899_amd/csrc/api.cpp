@@ -670,7 +670,7 @@ int run_large(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* sta
     {
       LargeArgs r = with_grid(0);
       r.nb = tuned_reduction_nb(max_m, fp64);
-      r.red_per_cu = tuned_reduction_per_cu(max_m, fp64);
+      r.red_per_cu = reduction_fit_per_cu(max_m, r.nb, fp64, ctx->lds_limit, tuned_reduction_per_cu(max_m, fp64));
       if (!per_column) r.grid = persistent_grid(ctx, count, r.red_per_cu);
       next();
       r.work_ctr = a.work_ctr;

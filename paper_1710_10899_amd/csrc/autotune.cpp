@@ -8,7 +8,10 @@
 //   3 / 4  panel width of the FP64 / FP32 tridiagonal reduction (even, 2..48)
 //   5 / 6  workgroups per compute unit the FP64 / FP32 reduction is laid
 //          out for (1..4: its LDS panel copy takes the rest of the share)
-// Defaults are the gfx950 measurements on the overlap workloads; a file
+// Defaults are the gfx950 measurements on the overlap workloads (the FP32
+// reduction runs three workgroups per compute unit: 118.5 against 137.0 ms
+// with two on the 6656-column workload, 869 against 981 ms on 26,624 columns
+// of order ~500; the FP64 one two: three spill and were slower); a file
 // written by the package's autotune script (environment variable
 // SUBMAT_TUNE_FILE, lines "kind m_hi value") overrides them.
 #include <cstdio>
@@ -34,7 +37,7 @@ void load_locked(bool use_file) {
   g_table = {{1, 128, 8}, {1, 256, 4}, {1, 1024, 2}, {1, 1 << 30, 1},
              {0, 128, 8}, {0, 256, 4}, {0, 1024, 2}, {0, 1 << 30, 1},
              {2, 256, 8}, {2, 512, 6}, {2, 1024, 4}, {2, 1 << 30, 1},
-             {3, 1 << 30, 16}, {4, 1 << 30, 16}, {5, 1 << 30, 2}, {6, 1 << 30, 2}};
+             {3, 1 << 30, 16}, {4, 1 << 30, 16}, {5, 1 << 30, 2}, {6, 1 << 30, 3}};
   g_from_file = false;
   const char* path = use_file ? std::getenv("SUBMAT_TUNE_FILE") : nullptr;
   if (path && *path) {

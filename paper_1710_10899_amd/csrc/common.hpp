@@ -104,20 +104,33 @@ __device__ __forceinline__ double group_sum(double v, int g) {
   return v;
 }
 
+// Value of lane l (a compile-time-uniform lane index), broadcast to every lane.
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave-wide reductions: within each row of 16 lanes by DPP exchanges (lane ^ 1,
+// lane ^ 2, the other quad of 8, the other 8 of 16: every lane of a row ends
+// with the same bits, the operation being commutative), then the four rows'
+// values from lanes 0, 16, 32, 48 combined in that order in every lane.
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_f64<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = op(v, dpp_f64<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = op(v, dpp_f64<0x141>(v));  // row_half_mirror
+  v = op(v, dpp_f64<0x140>(v));  // row_mirror
+  return op(op(op(read_lane(v, 0), read_lane(v, 16)), read_lane(v, 32)), read_lane(v, 48));
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  return wave_reduce(v, [](double x, double y) { return x + y; });
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
-  return v;
+  return wave_reduce(v, [](double x, double y) { return fmin(x, y); });
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, kWave));
-  return v;
+  return wave_reduce(v, [](double x, double y) { return fmax(x, y); });
 }
 
 // Block-wide sum over NW waves; `red` is LDS scratch of >= NW doubles.

@@ -14,6 +14,7 @@ enum StatusSlot : int {
   ST_INVITER = 3,     // eigenvectors computed by inverse iteration (eigenvalue clusters)
   ST_STALE = 4,       // columns whose order exceeds what the plan was built for (NaN output)
   ST_PATTERN = 5,     // calls whose pattern failed device-side validation (no output written)
+  ST_DONE = 6,        // columns whose output (forward column or adjoint terms) was written
   ST_NSLOTS = 64,
 };
 
@@ -142,6 +143,9 @@ enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 
 hipError_t launch_gather_large(const LargeArgs& a, hipStream_t s);
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s);
+// Workgroups per compute unit of the reduction: per_cu, lowered until each
+// workgroup's LDS share holds its fixed part and min(nb, max_m) panel rows.
+int reduction_fit_per_cu(int max_m, int nb, int fp64, int64_t lds_limit, int per_cu);
 int back_blocks_per_cu();       // the same for the back-transformation
 int adjoint_blocks_per_cu();    // and for the adjoint
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);

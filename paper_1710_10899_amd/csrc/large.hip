@@ -20,6 +20,8 @@
 // full Householder vector v_k (zeros above row k+1, 1 at row k+1).
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "gemm.hpp"
 #include "kernels.hpp"
@@ -130,7 +132,10 @@ constexpr int kRedBlock = kRedNW * kWave;
 // After a barrier, y = sum over waves of the partials, in a fixed order
 // (deterministic), is formed by the caller.
 constexpr int kStrip = 8;
-// row groups of 64 per strip iteration of the symv, by element type
+// row groups of 64 per strip iteration of the symv, by element type (two for
+// both: four groups of 4-byte elements raised the FP32 reduction's register
+// use past what three workgroups per compute unit allow, and were slower,
+// 141.9 against 137.0 ms on the 6656-column workload)
 template <class T> constexpr int kSymvGroups = 2;
 template <> constexpr int kSymvGroups<float> = 2;
 
@@ -1383,6 +1388,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
       for (int q = 0; q < m; ++q) s = fma((double)Q[(int64_t)q * ld + r], wv[q], s);
       x[r] = bad ? (VT)NAN : (VT)s;
     }
+    if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
   }
 }
 
@@ -1399,6 +1405,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_column(LargeArgs a) {
 // walks the columns of Z with y broadcast from LDS.
 constexpr int kColWavesPerCU = 16;
 
+// u <- H_k u for one reflector (orders above 16 * 64: the prefetching loop
+// below would hold three 32-element vectors per lane)
 template <class T, int NPL>
 __device__ __forceinline__ void apply_reflector(const T* __restrict__ v, double tk, int m, int lane, double (&u)[NPL]) {
   double d = 0.0;
@@ -1412,6 +1420,53 @@ __device__ __forceinline__ void apply_reflector(const T* __restrict__ v, double 
   for (int i = 0; i < NPL; ++i) {
     const int r = lane + kWave * i;
     if (r < m) u[i] = fma(-d, (double)v[r], u[i]);
+  }
+}
+
+// u <- H_k u for k = k0, k0 + dk, ..., k1 (inclusive, dk = +1 or -1), each
+// H_k = I - tau_k v_k v_k^T with v_k in column k of V (leading dimension ld,
+// rows >= m never read). Up to 16 rows per lane the next reflector's column
+// is loaded while the current one's dot product is reduced.
+template <class T, int NPL>
+__device__ __forceinline__ void apply_reflectors(const T* __restrict__ V, const T* __restrict__ tau, int ld, int m,
+                                                 int k0, int k1, int dk, int lane, double (&u)[NPL]) {
+  if ((k1 - k0) * dk < 0) return;
+  if constexpr (NPL > 16) {
+    for (int k = k0;; k += dk) {
+      apply_reflector<T, NPL>(V + (int64_t)k * ld, (double)tau[k], m, lane, u);
+      if (k == k1) break;
+    }
+    return;
+  }
+  double vn[NPL];
+#pragma unroll
+  for (int i = 0; i < NPL; ++i) {
+    const int r = lane + kWave * i;
+    vn[i] = r < m ? (double)V[(int64_t)k0 * ld + r] : 0.0;
+  }
+  double tn = (double)tau[k0];
+  for (int k = k0;; k += dk) {
+    double v[NPL];
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) v[i] = vn[i];
+    const double tk = tn;
+    const bool more = k != k1;
+    if (more) {
+      const T* vc = V + (int64_t)(k + dk) * ld;
+#pragma unroll
+      for (int i = 0; i < NPL; ++i) {
+        const int r = lane + kWave * i;
+        vn[i] = r < m ? (double)vc[r] : 0.0;
+      }
+      tn = (double)tau[k + dk];
+    }
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) d = fma(v[i], u[i], d);
+    d = tk * wave_sum(d);
+#pragma unroll
+    for (int i = 0; i < NPL; ++i) u[i] = fma(-d, v[i], u[i]);
+    if (!more) break;
   }
 }
 
@@ -1447,7 +1502,7 @@ __global__ __launch_bounds__(kWave) void k_column_factored(LargeArgs a) {
 #pragma unroll
     for (int i = 0; i < NPL; ++i) u[i] = (lane + kWave * i == c) ? 1.0 : 0.0;
     // u = Q1^T e_c = H_{m-3} ... H_0 e_c
-    for (int k = 0; k + 2 < m; ++k) apply_reflector<T, NPL>(V + (int64_t)k * ld, (double)tau[k], m, lane, u);
+    apply_reflectors<T, NPL>(V, tau, ld, m, 0, m - 3, 1, lane, u);
     // y = f(lambda) o (Z^T u), eight columns of Z per pass
     for (int j0 = 0; j0 < m; j0 += kStrip) {
       double cd[kStrip];
@@ -1482,12 +1537,13 @@ __global__ __launch_bounds__(kWave) void k_column_factored(LargeArgs a) {
       }
     }
     // x = Q1 u = H_0 ... H_{m-3} u
-    for (int k = m - 3; k >= 0; --k) apply_reflector<T, NPL>(V + (int64_t)k * ld, (double)tau[k], m, lane, u);
+    apply_reflectors<T, NPL>(V, tau, ld, m, m - 3, 0, -1, lane, u);
 #pragma unroll
     for (int i = 0; i < NPL; ++i) {
       const int r = lane + kWave * i;
       if (r < m) x[r] = bad ? (VT)NAN : (VT)u[i];
     }
+    if (lane == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
     __syncthreads();
   }
 }
@@ -1563,6 +1619,7 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
       for (int lo = wv; lo < m; lo += kAdjNW)
         for (int hi = lo + lane; hi < m; hi += kWave)
           D64[(int64_t)lo * ld + hi] = bad ? (double)NAN : (double)Ms[(int64_t)lo * ld + hi];
+      if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
       __syncthreads();
       continue;
     }
@@ -1578,6 +1635,7 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
         }
       }
     }
+    if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
   }
 }
 
@@ -1614,6 +1672,27 @@ int adjoint_blocks_per_cu() { return kAdjPerCU; }
 // coefficients, panel dots) plus a margin
 constexpr size_t kTridiagStaticLds = 4096;
 
+// Rows of the LDS panel copy that a workgroup's share of the LDS holds, with
+// per_cu workgroups per compute unit (negative: the fixed part alone does
+// not fit that share), up to the largest order.
+static int reduction_panel_rows(int max_m, int nb, int fp64, int64_t lds_limit, int per_cu) {
+  const size_t part = (size_t)kRedNW * max_m * 8;
+  const size_t gemm = fp64 ? gemm_lds_elems<kRedNW>() * sizeof(double) : gemm_lds_elems<kRedNW>() * sizeof(float);
+  const size_t base = (size_t)max_m * 8 + (part > gemm ? part : gemm);
+  const int64_t left = lds_limit / per_cu - (int64_t)base - (int64_t)kTridiagStaticLds;
+  if (left < 0) return -1;
+  const int64_t rows = left / (2 * (nb + 1) * (int64_t)sizeof(double));
+  return (int)(rows < max_m ? rows : max_m);
+}
+
+int reduction_fit_per_cu(int max_m, int nb, int fp64, int64_t lds_limit, int per_cu) {
+  // fewer workgroups per compute unit until each one's share of the LDS
+  // also holds one panel width of rows of the panel copy (more would not be
+  // resident together anyway, and would only cost registers)
+  while (per_cu > 1 && reduction_panel_rows(max_m, nb, fp64, lds_limit, per_cu) < std::min(nb, max_m)) --per_cu;
+  return per_cu;
+}
+
 template <class T, int PERCU>
 static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
   LargeArgs a = a0;
@@ -1622,9 +1701,8 @@ static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
   const size_t base = vec_lds(a, 1, 8) + (part > gemm ? part : gemm);
   // the panel copy takes what is left of the workgroup's share of the LDS
   // (PERCU workgroups per compute unit), up to the largest order
-  const int64_t left = (int64_t)a.lds_limit / PERCU - (int64_t)base - (int64_t)kTridiagStaticLds;
-  int rows = left > 0 ? (int)(left / (2 * pld * sizeof(double))) : 0;
-  if (rows > a.max_m) rows = a.max_m;
+  int rows = reduction_panel_rows(a.max_m, a.nb, a.fp64, a.lds_limit, PERCU);
+  if (rows < 0) rows = 0;
   a.panel_rows = rows;
   a.panel_off = (int)((part > gemm ? part : gemm) / sizeof(double));
   const size_t lds = base + (size_t)rows * 2 * pld * sizeof(double);
@@ -1634,6 +1712,8 @@ static void launch_tridiag_t(const LargeArgs& a0, hipStream_t s) {
 hipError_t launch_tridiagonalise(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.nb < 2 || a.nb > kNBMax || (a.nb & 1) || a.red_per_cu < 1 || a.red_per_cu > 4) return hipErrorInvalidValue;
+  if (reduction_fit_per_cu(a.max_m, a.nb, a.fp64, a.lds_limit, a.red_per_cu) != a.red_per_cu)
+    return hipErrorInvalidValue;  // the caller sizes the grid for the value that fits
   if (a.fp64) {
     switch (a.red_per_cu) {
       case 1: launch_tridiag_t<double, 1>(a, s); break;

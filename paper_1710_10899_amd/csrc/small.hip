@@ -297,6 +297,7 @@ __global__ __launch_bounds__(64) void k_small(SmallArgs args) {
       else
         finish_forward<double, VT, MMAX>(V, sh, m, c, args.fn, bad, (VT*)args.x + a0);
     }
+    if (lane == 0) atomicAdd((unsigned long long*)&args.status[ST_DONE], 1ull);
   }
 }
 

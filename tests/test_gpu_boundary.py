@@ -166,3 +166,37 @@ def test_int64_csr_patterns_with_equal_n_and_nnz(gpu_lib):
         assert torch.equal(x.crow_indices(), a.crow_indices()) and torch.equal(x.col_indices(), a.col_indices())
         del a, x
         gc.collect()
+
+
+@pytest.mark.parametrize("small_max", [16, 40, 64])
+def test_every_column_processed_exactly_once(small_max, gpu_lib):
+    """Status slot 6 counts the columns whose output a call wrote: it equals
+    n for the forward and the adjoint whatever the split between the
+    one-wavefront and the large-order buckets (bucket edge small_max), the
+    number of workspace chunks, the precision passes (FP32 with forced FP64
+    redos) or the per-column path."""
+    import torch
+    import paper_1710_10899_amd as sm
+    from paper_1710_10899_amd import _lib
+    csr = G.block_diagonal_spd((1, 7, 13, 30, 50, 64, 100, 140), kappa=40.0, permute=True)
+    w = G.upstream_gradient(csr, G.BASE_SEED + 180)
+    s = torch.cuda.current_stream().cuda_stream
+    try:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, small_max)
+        for budget in (0.0, 3e6):
+            _lib.submat_set_option(_lib.SUBMAT_OPT_WS_BYTES, budget)
+            rp, ci, va = to_dev(csr)
+            gx = torch.from_numpy(w).cuda()
+            for precision, kmax in (("f64", 1e5), ("f32_mixed", 1e5), ("f32_mixed", 2.0), ("f64_plain", 1e5)):
+                _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, kmax)
+                banner(f"columns once: small_max={small_max} budget={budget:g} {precision} kappa_max={kmax:g}")
+                sm.invroot_fwd(rp, ci, va, 2, precision)
+                nf = _lib.submat_query_counters(s, 7)[6]
+                sm.invroot_bwd(rp, ci, va, gx, 2, precision)
+                nb = _lib.submat_query_counters(s, 7)[6]
+                assert nf == csr.n and nb == csr.n, (nf, nb, csr.n)
+            _lib.submat_release()
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, 1e5)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_WS_BYTES, 0.0)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 64)

@@ -127,6 +127,13 @@ extern "C" {
                                     the order distribution) and leaves the other columns'
                                     outputs unwritten; k >= 1, default 1 (every column).
                                     No other precision looks at it. */
+#define SUBMAT_OPT_XCD_QUEUES 9 /* 1 (default): the launches over (submatrix, column block)
+                                    units of the back-transformation and of the adjoint's
+                                    products take their units from eight queues, one per
+                                    XCD, each holding every eighth submatrix, so that the
+                                    units of one submatrix run together on one XCD and
+                                    share its L2; 0: one queue in submatrix order. Results
+                                    are bit-identical either way. */
 
 /* spectral function f applied to every submatrix, and the meaning of `param` */
 #define SUBMAT_FN_INV_ROOT 0  /* f(lambda) = lambda^(-1/p), param = p, integer >= 1 (Sections 3-4) */

@@ -43,6 +43,7 @@ SUBMAT_OPT_CLUSTER_TOL = 5
 SUBMAT_OPT_TUNE_FILE = 6
 SUBMAT_OPT_DETERMINISTIC = 7
 SUBMAT_OPT_PLAIN_STRIDE = 8
+SUBMAT_OPT_XCD_QUEUES = 9
 SUBMAT_NUM_PHASES = 10
 
 PHASES = ["plan-reset", "small-jacobi", "gather", "tridiagonalise", "tridiagonal-eig", "reorthogonalise",

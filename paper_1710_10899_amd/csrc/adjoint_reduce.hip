@@ -67,6 +67,35 @@ __global__ __launch_bounds__(kRedBlock) void k_adjoint_reduce(DetReduceArgs a) {
   }
 }
 
+// The atomic scatter-adds write the lower triangle (column <= row) only;
+// afterwards every upper entry q = (r, c), c > r, adds the value of its
+// lower mirror (c, r) at tpos[q]. Upper entries hold zero at that point,
+// or NaN where a column marked its segment as not computed.
+template <class VT>
+__global__ __launch_bounds__(kRedBlock) void k_adjoint_mirror(const int32_t* __restrict__ rowptr,
+                                                              const int32_t* __restrict__ colind,
+                                                              const int32_t* __restrict__ tpos, int n, VT* ga) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  for (int r = blockIdx.x * kRedWaves + wv; r < n; r += gridDim.x * kRedWaves) {
+    const int r0 = rowptr[r], r1 = rowptr[r + 1];
+    for (int q = r0 + lane; q < r1; q += kWave)
+      if (colind[q] > r) ga[q] += ga[tpos[q]];
+  }
+}
+
+hipError_t launch_adjoint_mirror(const int32_t* rowptr, const int32_t* colind, const int32_t* tpos, int n,
+                                 void* ga, int vdtype, int num_cus, hipStream_t s) {
+  int g = (n + kRedWaves - 1) / kRedWaves;
+  if (g > num_cus * 8) g = num_cus * 8;
+  if (g < 1) g = 1;
+  if (vdtype == 0)
+    hipLaunchKernelGGL(k_adjoint_mirror<double>, dim3(g), dim3(kRedBlock), 0, s, rowptr, colind, tpos, n, (double*)ga);
+  else
+    hipLaunchKernelGGL(k_adjoint_mirror<float>, dim3(g), dim3(kRedBlock), 0, s, rowptr, colind, tpos, n, (float*)ga);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint_reduce(const DetReduceArgs& a, int vdtype, int num_cus, hipStream_t s) {
   int g = (a.n + kRedWaves - 1) / kRedWaves;
   if (g > num_cus * 8) g = num_cus * 8;

@@ -33,6 +33,7 @@ struct Options {
   double cluster_tol = 1e-5;
   int deterministic = 0;   // adjoint assembled in a fixed order instead of by atomic adds
   int plain_stride = 1;    // the per-column path computes every plain_stride-th column only
+  int xcd_queues = 1;      // unit launches take their work from one queue per XCD
   uint64_t tune_gen = 0;   // bumped whenever the tuning table is reloaded
 };
 Options g_opt;
@@ -402,8 +403,8 @@ int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int
       (rc = P.d_dld.alloc(n)) || (rc = P.d_doff.alloc(n)))
     return rc;
   // one work counter per persistent launch of the longest sequence (the
-  // per-column path launches up to 7 kernels per column)
-  P.ncounters = 64 + 32 * (int)P.chunks.size() + 8 * n;
+  // per-column path launches up to 10 kernels per column)
+  P.ncounters = 64 + 128 * (int)P.chunks.size() + 16 * n;
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (!bytes) return hipSuccess;
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
@@ -651,6 +652,15 @@ int run_large(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* sta
   a.grid = per_column ? 1 : persistent_grid(ctx, count, tune_cu);
   const int ph = only_flagged ? PH_FALLBACK : -1;
   auto next = [&]() { a.work_ctr = W.counters.p + (ctr++ % P.ncounters); };
+  // unit launches: one counter, or one per XCD queue (consecutive; the
+  // counter budget of a batched call leaves room for them without wrapping)
+  const int queues = (!per_column && g_opt.xcd_queues) ? kXcdQueueCount : 1;
+  auto next_units = [&](LargeArgs& b) {
+    if (ctr % P.ncounters + queues > P.ncounters) ctr += P.ncounters - ctr % P.ncounters;
+    b.work_ctr = W.counters.p + (ctr % P.ncounters);
+    b.xcd_queues = queues > 1;
+    ctr += queues;
+  };
   // Kernels whose registers and LDS leave room for more workgroups per
   // compute unit than the tuned value get at least that many (measured on
   // the overlap workloads: the gather, the column and the
@@ -690,12 +700,28 @@ int run_large(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* sta
     // the eigenvector matrix Q = Q1 Z is formed only where it is used: by the
     // adjoint, or kept in a saved buffer for a later adjoint
     if (c.bwd || c.saved) {
-      next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_transform(with_grid(back_blocks_per_cu()), s));
+      next(); HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_prep(with_grid(back_blocks_per_cu()), s));
+      {
+        // the column units: a grid over units rather than items
+        LargeArgs b = with_grid(back_blocks_per_cu());
+        if (!per_column) b.grid = persistent_grid(ctx, back_apply_units(count, max_m), back_blocks_per_cu());
+        next_units(b);
+        HIP_SEQ(ph < 0 ? PH_BACK : ph, launch_back_apply(b, s));
+      }
     }
   }
   next();
-  if (c.bwd) HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint(with_grid(adjoint_blocks_per_cu()), s));
-  else if (c.saved) HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
+  if (c.bwd) {
+    HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint_prep(with_grid(adjoint_blocks_per_cu()), s));
+    LargeArgs b = with_grid(adjoint_blocks_per_cu());
+    if (!per_column) b.grid = persistent_grid(ctx, back_apply_units(count, max_m), adjoint_blocks_per_cu());
+    for (int lower = 0; lower < 2; ++lower) {
+      next_units(b);
+      HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint_product(b, lower, s));
+    }
+    next();
+    HIP_SEQ(ph < 0 ? PH_ADJOINT : ph, launch_adjoint_scatter(with_grid(adjoint_blocks_per_cu()), s));
+  } else if (c.saved) HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_apply_column(with_grid(8), s));
   else HIP_SEQ(ph < 0 ? PH_COLUMN : ph, launch_column_factored(with_grid(column_waves_per_cu()), s));
   return SUBMAT_OK;
 }
@@ -781,6 +807,9 @@ int run_sequence(Plan& P, Workspace& W, DeviceCtx* ctx, const Call& c, int64_t* 
     if (c.bwd && c.det)
       HIP_SEQ(PH_ADJOINT, launch_adjoint_reduce(det_args(P, c, 1 + ci, W.W.p, 1), c.vdtype, ctx->num_cus, s));
   }
+  // the atomic scatter-adds fill the lower triangle; the upper one mirrors it
+  if (c.bwd && !c.det)
+    HIP_SEQ(PH_ADJOINT, launch_adjoint_mirror(P.rowptr, P.colind, P.tpos.p, P.n, c.ga, c.vdtype, ctx->num_cus, s));
   return SUBMAT_OK;
 }
 
@@ -1280,6 +1309,10 @@ int submat_set_option(int32_t key, double value) {
       if (!(value >= 1.0 && value <= 1e9) || value != std::floor(value)) return SUBMAT_EINVAL;
       g_opt.plain_stride = (int)value;
       return SUBMAT_OK;
+    case SUBMAT_OPT_XCD_QUEUES:
+      if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
+      g_opt.xcd_queues = (int)value;
+      return SUBMAT_OK;
     default:
       return SUBMAT_EINVAL;
   }
@@ -1296,6 +1329,7 @@ double submat_get_option(int32_t key) {
     case SUBMAT_OPT_TUNE_FILE: return tuning_from_file() ? 1.0 : 0.0;
     case SUBMAT_OPT_DETERMINISTIC: return g_opt.deterministic;
     case SUBMAT_OPT_PLAIN_STRIDE: return g_opt.plain_stride;
+    case SUBMAT_OPT_XCD_QUEUES: return g_opt.xcd_queues;
     default: return NAN;
   }
 }

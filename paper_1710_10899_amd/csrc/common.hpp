@@ -169,6 +169,39 @@ __device__ __forceinline__ int next_item(int* ctr, int* s_slot) {
   return __builtin_amdgcn_readfirstlane(*s_slot);
 }
 
+// Work queues grouped by XCD for launches over (item, block) units, item-
+// major (u = it * ncb + cb): queue q holds the items it = q, q + 8, ... A
+// workgroup takes units from the queue of the XCD it runs on (the XCC_ID
+// hardware register), then from the others in turn, so every unit is taken
+// exactly once whatever the placement, and the units of one item, taken at
+// about the same time by workgroups of one XCD, share that XCD's L2.
+// ctrs: kXcdQueues counters, zero at launch. Returns u, or -1 once every
+// queue is drained. `q` (thread 0's) carries the current queue between calls.
+constexpr int kXcdQueues = 8;
+__device__ __forceinline__ int xcc_id() {
+  // s_getreg_b32 of HW_REG_XCC_ID (id 20), bits 3:0
+  return __builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (kXcdQueues - 1);
+}
+__device__ __forceinline__ int next_unit_xcd(int* ctrs, int n_items, int ncb, int* s_slot, int& q) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int res = -1;
+    for (int t = 0; t < kXcdQueues; ++t) {
+      const int qq = (q + t) & (kXcdQueues - 1);
+      const int nq = (n_items - qq + kXcdQueues - 1) / kXcdQueues;  // items of queue qq
+      const int l = atomicAdd(&ctrs[qq], 1);
+      if (l < nq * ncb) {
+        res = (qq + kXcdQueues * (l / ncb)) * ncb + (l % ncb);
+        q = qq;
+        break;
+      }
+    }
+    *s_slot = res;
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*s_slot);
+}
+
 template <class T>
 __device__ __forceinline__ void atomic_add_val(T* p, T v) {
   atomicAdd(p, v);

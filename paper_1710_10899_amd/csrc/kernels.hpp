@@ -92,6 +92,10 @@ struct DetReduceArgs {
   void* ga;               // accumulated in place (zeroed at the start of the call)
 };
 hipError_t launch_adjoint_reduce(const DetReduceArgs& a, int vdtype, int num_cus, hipStream_t s);
+// upper entries of grad_a += their lower mirrors (after the lower-triangle
+// scatter-adds of every phase)
+hipError_t launch_adjoint_mirror(const int32_t* rowptr, const int32_t* colind, const int32_t* tpos, int n,
+                                 void* ga, int vdtype, int num_cus, hipStream_t s);
 
 // ---- large-order path (large.hip) ----
 struct LargeArgs {
@@ -138,6 +142,7 @@ struct LargeArgs {
   int only_flagged;       // 1: process only items whose fallback flag is set
   int det;                // backward: leave D_j (FP64, lower triangle) in the W slab instead of
                           // scatter-adding it (deterministic assembly afterwards)
+  int xcd_queues;         // unit launches: work_ctr holds kXcdQueues counters, one queue per XCD
 };
 enum LargeFlags : int32_t { LF_NONPOS = 1, LF_FALLBACK = 2, LF_UNCONV = 4 };
 
@@ -150,7 +155,12 @@ int back_blocks_per_cu();       // the same for the back-transformation
 int adjoint_blocks_per_cu();    // and for the adjoint
 hipError_t launch_tridiag_eig(const LargeArgs& a, hipStream_t s);
 hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s);
-hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s);
+// back-transformation Q = Q1 Z: VT = V T^T per item and reflector block,
+// then the blocks applied per (item, column block) unit
+hipError_t launch_back_prep(const LargeArgs& a, hipStream_t s);
+hipError_t launch_back_apply(const LargeArgs& a, hipStream_t s);
+int back_apply_units(int n_items, int max_m);  // units of launch_back_apply
+constexpr int kXcdQueueCount = 8;               // work queues of a unit launch with xcd_queues
 size_t eig_lds_bytes(int max_m);
 size_t apply_scratch_elems(int ld);  // scratch elements per item of the back-transformation
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
@@ -158,6 +168,10 @@ hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s);
 // (one wavefront per submatrix)
 hipError_t launch_column_factored(const LargeArgs& a, hipStream_t s);
 int column_waves_per_cu();
-hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s);
+// adjoint: a, b and Ms per item; T1 = Q Ms and D = T1 Q^T (lower) over
+// (item, column block) units (units: back_apply_units); D into grad_a
+hipError_t launch_adjoint_prep(const LargeArgs& a, hipStream_t s);
+hipError_t launch_adjoint_product(const LargeArgs& a, int lower, hipStream_t s);
+hipError_t launch_adjoint_scatter(const LargeArgs& a, hipStream_t s);
 
 }  // namespace submat

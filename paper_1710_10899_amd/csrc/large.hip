@@ -21,6 +21,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "common.hpp"
 #include "gemm.hpp"
@@ -1255,12 +1256,23 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
 // T is upper triangular: for a half of kNBh reflectors, T[c][c] = tau_c
 // and T[0:c, c] = -tau_c T[0:c, 0:c] (V^T V)[0:c, c] (one wave, in LDS);
 // the two halves merge as [[T1, -T1 (V1^T V2) T2], [0, T2]]. All products
-// on MFMA; 2 m^3 flops in all, and one read and write of Q per block.
+// on MFMA; 2 m^3 flops in all.
+// Two kernels: k_back_prep forms, per item and block, VT = V T^T into the
+// W slab at V's position; k_back_apply then takes (item, kBackCols columns
+// of Q) units, independent of each other since the blocks act on the rows:
+// each applies every block to its columns, so Q crosses HBM about once per
+// block while the V and VT panels, read by all column units of an item,
+// come from the caches.
 constexpr int kNBq = 128;
 constexpr int kNBh = kNBq / 2;
+constexpr int kBackCols = 64;
+static_assert(kXcdQueues == kXcdQueueCount, "one work queue per XCD on both sides");
 
 size_t apply_scratch_elems(int ld) {
-  return 2 * (size_t)kNBq * kNBq + (size_t)kNBh * kNBh + 2 * (size_t)kNBq * ld;
+  // G, T, X, then Wm (kNBq x ld) for the column units; ld rounded up to
+  // whole column blocks
+  const size_t ldc = ((size_t)ld + kBackCols - 1) / kBackCols * kBackCols;
+  return 2 * (size_t)kNBq * kNBq + (size_t)kNBh * kNBh + (size_t)kNBq * ldc;
 }
 
 // Upper-triangular compact-WY factor of reflectors c0 .. c0+nh-1 of a block
@@ -1300,7 +1312,7 @@ __device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh,
 }
 
 template <class T>
-__global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_apply_reflectors(LargeArgs a) {
+__global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_prep(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   __shared__ double Ts[kNBh * kNBh];
@@ -1315,23 +1327,18 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_apply_reflectors(Lar
     const int ld = a.ldm[it];
     if (order_mismatch(a, m, ld)) continue;
     const T* S = at<T>((const void*)a.S, a.off[it]);
-    T* Q = at<T>(a.Q, a.qoff[it]);
+    T* VTs = at<T>(a.W, a.off[it]);
     const T* tau = at<T>((const void*)a.tau, a.voff[it]);
-    // scratch (type T): G, T (kNBq x kNBq each), X (kNBh x kNBh),
-    // VT (ld x kNBq), Wm (kNBq x ld)
+    // scratch (type T): G, T (kNBq x kNBq each), X (kNBh x kNBh)
     T* Gm = at<T>(a.escr, a.eoff[it]);
     T* Tm = Gm + kNBq * kNBq;
     T* Xm = Tm + kNBq * kNBq;
-    T* VT = Xm + kNBh * kNBh;
-    T* Wm = VT + (int64_t)kNBq * ld;
     const int nref = m - 2;
-    for (int t = (nref + kNBq - 1) / kNBq - 1; t >= 0; --t) {
-      const int k0 = t * kNBq;
+    for (int k0 = 0; k0 < nref; k0 += kNBq) {
       const int nbt = (nref - k0) < kNBq ? (nref - k0) : kNBq;
       const int n2 = m - k0 - 1;
       const int nh1 = nbt < kNBh ? nbt : kNBh, nh2 = nbt - nh1;
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
-      T* Qs = Q + (k0 + 1);
       wg_gemm<T, kBackNW, true, false, false, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
       for (int q = tid; q < kNBq * kNBq; q += kBackBlock) Tm[q] = T(0);
       __syncthreads();
@@ -1345,10 +1352,52 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_apply_reflectors(Lar
         wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
                                                    Tm + (int64_t)kNBh * kNBq, kNBq, gsm);
       }
-      // VT = V T^T (n2 x nbt), Wm = VT^T Q_sub (nbt x m), Q_sub -= V Wm
-      wg_gemm<T, kBackNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0), VT, ld, gsm);
-      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, m, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
-      wg_gemm<T, kBackNW, false, false, false, 1>(n2, m, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
+      // VT = V T^T (n2 x nbt) over V's position in the W slab
+      wg_gemm<T, kBackNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0),
+                                                VTs + (int64_t)k0 * ld + (k0 + 1), ld, gsm);
+    }
+  }
+}
+
+// Units u = it * ncb + cb over the items and their column blocks (ncb from
+// the largest order; units past an item's order are skipped).
+template <class T>
+__global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_apply(LargeArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ int s_item;
+  T* gsm = (T*)dyn;
+  const int ncb = (a.max_m + kBackCols - 1) / kBackCols;
+  const int nunits = a.n_items * ncb;
+  int q = xcc_id();
+  for (;;) {
+    const int u = a.xcd_queues ? next_unit_xcd(a.work_ctr, a.n_items, ncb, &s_item, q)
+                               : next_item(a.work_ctr, &s_item);
+    if (u < 0 || u >= nunits) break;
+    const int it = u / ncb, cb = u - it * ncb;
+    if (skip_item(a, it)) continue;
+    const int j = a.items[it];
+    const int m = a.rowptr[j + 1] - a.rowptr[j];
+    const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
+    const int c0 = cb * kBackCols;
+    if (c0 >= m) continue;
+    const int nc = (m - c0) < kBackCols ? (m - c0) : kBackCols;
+    const T* S = at<T>((const void*)a.S, a.off[it]);
+    const T* VTs = at<T>((const void*)a.W, a.off[it]);
+    T* Q = at<T>(a.Q, a.qoff[it]) + (int64_t)c0 * ld;
+    // this unit's columns of the kNBq x ld block product Wm
+    T* Wm = at<T>(a.escr, a.eoff[it]) + 2 * kNBq * kNBq + kNBh * kNBh + (int64_t)c0 * kNBq;
+    const int nref = m - 2;
+    for (int t = (nref + kNBq - 1) / kNBq - 1; t >= 0; --t) {
+      const int k0 = t * kNBq;
+      const int nbt = (nref - k0) < kNBq ? (nref - k0) : kNBq;
+      const int n2 = m - k0 - 1;
+      const T* V = S + (int64_t)k0 * ld + (k0 + 1);
+      const T* VT = VTs + (int64_t)k0 * ld + (k0 + 1);
+      T* Qs = Q + (k0 + 1);
+      // Wm = VT^T Q_sub (nbt x nc), Q_sub -= V Wm
+      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, nc, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
+      wg_gemm<T, kBackNW, false, false, false, 1>(n2, nc, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
     }
   }
 }
@@ -1552,22 +1601,25 @@ __global__ __launch_bounds__(kWave) void k_column_factored(LargeArgs a) {
 // a = Q^T w, b = Q[c,:]^T, Ms = (G o (a b^T + b a^T))/2, T1 = Q Ms,
 // D = T1 Q^T (lower tiles; D is symmetric), then every stored pair
 // (R[k], R[l]) at position q receives D[max(k,l)][min(k,l)].
+// Four kernels: k_adj_prep per item (a = Q^T w, b = Q[c, :]^T and Ms in the
+// S slab), then two products over (item, kBackCols columns) units, which
+// read the item's whole Q (or T1) from the caches while each writes only its
+// own columns: T1 = Q Ms into the W slab, D = T1 Q^T (lower part) into the
+// S slab; k_adj_scatter last, per item, adds D into grad_a (or, in the
+// deterministic mode, copies it to FP64 in the W slab).
 template <class T, class VT, bool POW>
-__global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
+__global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_prep(LargeArgs a) {
   extern __shared__ double dyn[];
   __shared__ int s_item;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  int* R = (int*)dyn;
-  double* w = dyn + (a.max_m + 1) / 2 + 1;
+  double* w = dyn;
   double* av = w + a.max_m;
   double* bv = av + a.max_m;
   double* alv = bv + a.max_m;
-  T* gsm = (T*)(alv + a.max_m);
   for (;;) {
     const int it = next_item(a.work_ctr, &s_item);
     if (it >= a.n_items) break;
     if (skip_item(a, it)) continue;
-    const int fl = a.flags[it];
     const int j = a.items[it];
     const int a0 = a.rowptr[j];
     const int m = a.rowptr[j + 1] - a0;
@@ -1580,12 +1632,9 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
     const int c = a.cidx[j];
     const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
     T* Ms = at<T>(a.S, a.off[it]);
-    T* T1 = at<T>(a.W, a.off[it]);
     const T* lam = at<T>((const void*)a.d, a.doff[it]);
-    const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
     const VT* gx = (const VT*)a.gx + a0;
     for (int i = tid; i < m; i += kAdjBlock) {
-      R[i] = a.colind[a0 + i];
       w[i] = (double)gx[i];
       bv[i] = (double)Q[(int64_t)i * ld + c];
       alv[i] = spec_node((double)lam[i], a.fn);
@@ -1610,8 +1659,63 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
       }
     }
     __syncthreads();
-    wg_gemm<T, kAdjNW, false, false, false, 1>(m, m, m, T(1), Q, ld, Ms, ld, T(0), T1, ld, gsm);
-    wg_gemm<T, kAdjNW, false, true, true, 1>(m, m, m, T(1), T1, ld, Q, ld, T(0), Ms, ld, gsm);
+  }
+}
+
+// LOWER = false: T1[:, c0:c0+nc] = Q Ms[:, c0:c0+nc] into the W slab;
+// LOWER = true:  D[c0:, c0:c0+nc] = T1[c0:, :] Q[c0:c0+nc, :]^T into the S slab
+// (the tiles of the block that meet the lower triangle).
+template <class T, bool LOWER>
+__global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_product(LargeArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ int s_item;
+  T* gsm = (T*)dyn;
+  const int ncb = (a.max_m + kBackCols - 1) / kBackCols;
+  const int nunits = a.n_items * ncb;
+  int q = xcc_id();
+  for (;;) {
+    const int u = a.xcd_queues ? next_unit_xcd(a.work_ctr, a.n_items, ncb, &s_item, q)
+                               : next_item(a.work_ctr, &s_item);
+    if (u < 0 || u >= nunits) break;
+    const int it = u / ncb, cb = u - it * ncb;
+    if (skip_item(a, it)) continue;
+    const int j = a.items[it];
+    const int m = a.rowptr[j + 1] - a.rowptr[j];
+    const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
+    const int c0 = cb * kBackCols;
+    if (c0 >= m) continue;
+    const int nc = (m - c0) < kBackCols ? (m - c0) : kBackCols;
+    const T* Q = at<T>((const void*)a.Q, a.qoff[it]);
+    T* Ms = at<T>(a.S, a.off[it]);
+    T* T1 = at<T>(a.W, a.off[it]);
+    if (!LOWER)
+      wg_gemm<T, kAdjNW, false, false, false, 1>(m, nc, m, T(1), Q, ld, Ms + (int64_t)c0 * ld, ld, T(0),
+                                                 T1 + (int64_t)c0 * ld, ld, gsm);
+    else
+      wg_gemm<T, kAdjNW, false, true, true, 1>(m - c0, nc, m, T(1), T1 + c0, ld, Q + c0, ld, T(0),
+                                               Ms + (int64_t)c0 * ld + c0, ld, gsm);
+  }
+}
+
+template <class T, class VT>
+__global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_scatter(LargeArgs a) {
+  extern __shared__ double dyn[];
+  __shared__ int s_item;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  int* R = (int*)dyn;
+  for (;;) {
+    const int it = next_item(a.work_ctr, &s_item);
+    if (it >= a.n_items) break;
+    if (skip_item(a, it)) continue;
+    const int fl = a.flags[it];
+    const int j = a.items[it];
+    const int a0 = a.rowptr[j];
+    const int m = a.rowptr[j + 1] - a0;
+    const int ld = a.ldm[it];
+    if (order_mismatch(a, m, ld)) continue;
+    const T* Ms = at<T>((const void*)a.S, a.off[it]);
+    const bool bad = (fl & (LF_NONPOS | LF_UNCONV)) != 0;
     if (a.det) {
       // deterministic mode: D (lower triangle, FP64) into this item's W slot
       // (T1 is dead), assembled afterwards in a fixed order
@@ -1620,15 +1724,20 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
         for (int hi = lo + lane; hi < m; hi += kWave)
           D64[(int64_t)lo * ld + hi] = bad ? (double)NAN : (double)Ms[(int64_t)lo * ld + hi];
       if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
-      __syncthreads();
       continue;
     }
+    for (int i = tid; i < m; i += kAdjBlock) R[i] = a.colind[a0 + i];
+    __syncthreads();
     VT* ga = (VT*)a.ga;
+    // the lower triangle only (column <= row); the upper entries receive
+    // their lower mirror's sum after the last phase
     for (int k = wv; k < m; k += kAdjNW) {
       const int r = R[k];
       const int s0 = a.rowptr[r], s1 = a.rowptr[r + 1];
       for (int q = s0 + lane; q < s1; q += kWave) {
-        const int l = find_sorted(R, m, a.colind[q]);
+        const int cq = a.colind[q];
+        if (cq > r) break;
+        const int l = find_sorted(R, m, cq);
         if (l >= 0) {
           const int hi = l > k ? l : k, lo = l > k ? k : l;
           atomicAdd(&ga[q], bad ? (VT)NAN : (VT)Ms[(int64_t)lo * ld + hi]);
@@ -1636,6 +1745,7 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adjoint(LargeArgs a) {
       }
     }
     if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);
+    __syncthreads();
   }
 }
 
@@ -1754,14 +1864,26 @@ hipError_t launch_eig_orth(const LargeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_back_transform(const LargeArgs& a, hipStream_t s) {
+hipError_t launch_back_prep(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if (a.fp64)
-    hipLaunchKernelGGL(k_apply_reflectors<double>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 8, s, a);
+    hipLaunchKernelGGL(k_back_prep<double>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 8, s, a);
   else
-    hipLaunchKernelGGL(k_apply_reflectors<float>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 4, s, a);
+    hipLaunchKernelGGL(k_back_prep<float>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 4, s, a);
   return hipGetLastError();
 }
+
+hipError_t launch_back_apply(const LargeArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if ((int64_t)a.n_items * ((a.max_m + kBackCols - 1) / kBackCols) > INT32_MAX) return hipErrorInvalidValue;
+  if (a.fp64)
+    hipLaunchKernelGGL(k_back_apply<double>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 8, s, a);
+  else
+    hipLaunchKernelGGL(k_back_apply<float>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 4, s, a);
+  return hipGetLastError();
+}
+
+int back_apply_units(int n_items, int max_m) { return n_items * ((max_m + kBackCols - 1) / kBackCols); }
 
 hipError_t launch_apply_column(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
@@ -1799,20 +1921,45 @@ hipError_t launch_column_factored(const LargeArgs& a, hipStream_t s) {
 }
 
 template <class T, bool POW>
-static void dispatch_adjoint(const LargeArgs& a, size_t lds, hipStream_t s) {
-  SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adjoint<T, VT, POW>), dim3(a.grid), dim3(kAdjBlock), lds, s, a));
+static void dispatch_adj_prep(const LargeArgs& a, size_t lds, hipStream_t s) {
+  SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adj_prep<T, VT, POW>), dim3(a.grid), dim3(kAdjBlock), lds, s, a));
 }
 
-hipError_t launch_adjoint(const LargeArgs& a, hipStream_t s) {
+hipError_t launch_adjoint_prep(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
-  const size_t base = ((size_t)(a.max_m + 1) / 2 + 1) * 8 + vec_lds(a, 4, 8);
+  const size_t lds = vec_lds(a, 4, 8);
   const bool pw = a.fn.kind == FN_POWER;
+  if (a.fp64)
+    pw ? dispatch_adj_prep<double, true>(a, lds, s) : dispatch_adj_prep<double, false>(a, lds, s);
+  else
+    pw ? dispatch_adj_prep<float, true>(a, lds, s) : dispatch_adj_prep<float, false>(a, lds, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_product(const LargeArgs& a, int lower, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  if ((int64_t)a.n_items * ((a.max_m + kBackCols - 1) / kBackCols) > INT32_MAX) return hipErrorInvalidValue;
   if (a.fp64) {
-    const size_t lds = base + gemm_lds_elems<kAdjNW>() * sizeof(double);
-    pw ? dispatch_adjoint<double, true>(a, lds, s) : dispatch_adjoint<double, false>(a, lds, s);
+    if (lower)
+      hipLaunchKernelGGL((k_adj_product<double, true>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 8, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_product<double, false>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 8, s, a);
   } else {
-    const size_t lds = base + gemm_lds_elems<kAdjNW>() * sizeof(float);
-    pw ? dispatch_adjoint<float, true>(a, lds, s) : dispatch_adjoint<float, false>(a, lds, s);
+    if (lower)
+      hipLaunchKernelGGL((k_adj_product<float, true>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 4, s, a);
+    else
+      hipLaunchKernelGGL((k_adj_product<float, false>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 4, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_scatter(const LargeArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  const size_t lds = (size_t)a.max_m * sizeof(int);
+  if (a.fp64) {
+    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adj_scatter<double, VT>), dim3(a.grid), dim3(kAdjBlock), lds, s, a));
+  } else {
+    SUBMAT_VT_SWITCH(a.vdtype, hipLaunchKernelGGL((k_adj_scatter<float, VT>), dim3(a.grid), dim3(kAdjBlock), lds, s, a));
   }
   return hipGetLastError();
 }

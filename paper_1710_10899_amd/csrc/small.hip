@@ -214,10 +214,14 @@ __device__ void finish_backward(const T* V, SmallShared<MMAX>& sh, int m, int c,
     if (dout) {
       for (int l = lane; l < m; l += kWave) dout[(int64_t)k * m + l] = bad ? (double)NAN : sh.dk[l];
     } else {
+      // the lower triangle only (column <= row): D_j is symmetric, and the
+      // upper entries receive their lower mirror's sum after the last phase
       const int r = sh.R[k];
       const int s0 = rowptr[r], s1 = rowptr[r + 1];
       for (int q = s0 + lane; q < s1; q += kWave) {
-        const int l = find_sorted(sh.R, m, colind[q]);
+        const int cq = colind[q];
+        if (cq > r) break;
+        const int l = find_sorted(sh.R, m, cq);
         if (l >= 0) atomicAdd(&ga[q], bad ? (VT)NAN : (VT)sh.dk[l]);
       }
     }

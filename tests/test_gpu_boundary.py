@@ -200,3 +200,47 @@ def test_every_column_processed_exactly_once(small_max, gpu_lib):
         _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, 1e5)
         _lib.submat_set_option(_lib.SUBMAT_OPT_WS_BYTES, 0.0)
         _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 64)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_mixed"])
+def test_xcd_queues_bit_identical(precision, gpu_lib):
+    """SUBMAT_OPT_XCD_QUEUES only changes which workgroup takes which
+    (submatrix, column block) unit of the back-transformation and of the
+    adjoint's products: the saved eigenvectors, the forward and the
+    (deterministic) adjoint are bit-identical with one queue per XCD and with
+    a single queue, and both equal the oracle."""
+    import torch
+    import paper_1710_10899_amd as sm
+    from paper_1710_10899_amd import _lib
+    csr = G.overlap_matrix(n_atoms=48, nbf=13, rcut=4.14, kappa=100.0, seed=85)
+    check_launch_shapes(csr)
+    w = G.upstream_gradient(csr, G.BASE_SEED + 190)
+    rp, ci, va = to_dev(csr)
+    gx = torch.from_numpy(w).cuda()
+    nb = sm.saved_bytes(rp, ci, torch.float64, precision)
+    outs = []
+    try:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_DETERMINISTIC, 1)
+        for queues in (1, 0):
+            _lib.submat_set_option(_lib.SUBMAT_OPT_XCD_QUEUES, queues)
+            banner(f"xcd queues={queues} {precision}")
+            saved = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+            x = sm.invroot_fwd(rp, ci, va, 2, precision, saved).cpu().numpy()
+            g1 = sm.invroot_bwd(rp, ci, va, gx, 2, precision, saved).cpu().numpy()
+            g2 = sm.invroot_bwd(rp, ci, va, gx, 2, precision).cpu().numpy()
+            outs.append((x, g1, g2, saved.cpu().numpy()))
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_XCD_QUEUES, 1)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_DETERMINISTIC, 0)
+    (x1, g11, g21, s1), (x0, g10, g20, s0) = outs
+    assert np.array_equal(s1, s0)
+    assert np.array_equal(x1.view(np.int64), x0.view(np.int64))
+    assert np.array_equal(g11.view(np.int64), g10.view(np.int64))
+    assert np.array_equal(g21.view(np.int64), g20.view(np.int64))
+    tol = TOL64 if precision == "f64" else TOL32
+    xr, _ = oracle.forward(csr.rowptr, csr.colind, csr.vals, csr.n, 2)
+    gr = oracle.adjoint(csr.rowptr, csr.colind, csr.vals, csr.n, 2, w)
+    ex, e1, e2 = rel_fro(x1, xr), rel_fro(g11, gr), rel_fro(g21, gr)
+    print(f"{precision}: forward {ex:.2e}, adjoint saved {e1:.2e}, recomputed {e2:.2e}", flush=True)
+    assert ex <= tol and e1 <= tol and e2 <= tol
+

@@ -63,6 +63,12 @@ def test_version_strerror_options_without_gpu():
         _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, 0.5)
     with pytest.raises(_lib.SubmatError):
         _lib.submat_set_option(999, 1.0)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_XCD_QUEUES) == 1
+    _lib.submat_set_option(_lib.SUBMAT_OPT_XCD_QUEUES, 0)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_XCD_QUEUES) == 0
+    _lib.submat_set_option(_lib.SUBMAT_OPT_XCD_QUEUES, 1)
+    with pytest.raises(_lib.SubmatError):
+        _lib.submat_set_option(_lib.SUBMAT_OPT_XCD_QUEUES, 2)
 
 
 def test_invalid_arguments_rejected_before_any_device_work():

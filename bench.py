@@ -42,8 +42,9 @@ WORKLOAD_NAMES = {
 # library kernel (substring of its symbol) -> phase of submat_time_phases
 KERNEL_PHASE = {"k_small": "small-jacobi", "k_gather_large": "gather", "k_tridiagonalise": "tridiagonalise",
                 "k_tridiag_eig": "tridiagonal-eig", "k_eig_orth": "reorthogonalise",
-                "k_apply_reflectors": "back-transform",
-                "k_apply_column": "apply-column", "k_adjoint": "adjoint", "k_plan_pattern": "plan-reset"}
+                "k_back_prep": "back-transform", "k_back_apply": "back-transform",
+                "k_apply_column": "apply-column", "k_column_factored": "apply-column",
+                "k_adj_": "adjoint", "k_adjoint": "adjoint", "k_plan_pattern": "plan-reset"}
 CSRC = os.path.join(ROOT, "paper_1710_10899_amd", "csrc")
 
 
@@ -233,8 +234,19 @@ def summarise_profile(d: str, command: str, workload: int, precision: str) -> No
         lines.append("| " + " | ".join(cells) + " |")
         want = "/f32" in (ph or "") if precision != "f64" else "/f32" not in (ph or "")
         if ph is not None and want and fb is not None and wb is not None:
-            phases[ph.replace("/f32", "")] = {"kernel": short, "avg_ms": ms, "fetch_bytes": fb, "write_bytes": wb,
-                                              "executed_flop": fl, "dram_share": share}
+            # a phase of several kernels (one launch each per pass) sums them
+            key = ph.replace("/f32", "")
+            if key in phases:
+                e = phases[key]
+                e["kernel"] += " + " + short
+                e["avg_ms"] += ms
+                e["fetch_bytes"] += fb
+                e["write_bytes"] += wb
+                e["executed_flop"] = (e["executed_flop"] or 0.0) + (fl or 0.0) if (e["executed_flop"] or fl) else None
+                e["dram_share"] = None
+            else:
+                phases[key] = {"kernel": short, "avg_ms": ms, "fetch_bytes": fb, "write_bytes": wb,
+                               "executed_flop": fl, "dram_share": share}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"{tag}_fwd_adjoint_{precision}.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")

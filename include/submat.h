@@ -106,7 +106,7 @@ extern "C" {
 #define SUBMAT_OPT_WS_BYTES 4    /* workspace budget per plan in bytes (0: automatic) */
 #define SUBMAT_OPT_CLUSTER_TOL 5 /* relative eigenvalue gap (times ||T||) below which the
                                     tridiagonal eigensolver computes eigenvectors by inverse
-                                    iteration with reorthogonalisation (1e-5), in [0, 1) */
+                                    iteration with reorthogonalisation (1e-7), in [0, 1) */
 #define SUBMAT_OPT_TUNE_FILE 6   /* tuning table of workgroups per compute unit: set 1 to
                                     (re)read the file named by the environment variable
                                     SUBMAT_TUNE_FILE (lines "kind m_hi blocks_per_cu", as

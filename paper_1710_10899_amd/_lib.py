@@ -98,6 +98,15 @@ def load(path: str | None = None) -> ctypes.CDLL:
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is not built; run `python -m paper_1710_10899_amd.build` "
                            "(there is no CPU fallback)")
+    # One HIP runtime per process: torch ships its own libamdhip64 under the
+    # soname the library links against, so torch is loaded first and the
+    # library binds to that copy (loaded the other way round, torch would
+    # run on the system runtime and the tensors it hands over would not be
+    # valid in the library's calls).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

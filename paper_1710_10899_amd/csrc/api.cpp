@@ -30,7 +30,7 @@ struct Options {
   int use_graph = 1;
   int small_max = 64;
   double ws_bytes = 0.0;
-  double cluster_tol = 1e-5;
+  double cluster_tol = 1e-7;
   int deterministic = 0;   // adjoint assembled in a fixed order instead of by atomic adds
   int plain_stride = 1;    // the per-column path computes every plain_stride-th column only
   int xcd_queues = 1;      // unit launches take their work from one queue per XCD

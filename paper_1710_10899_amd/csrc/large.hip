@@ -485,8 +485,11 @@ __global__ __launch_bounds__(kRedBlock, PERCU) void k_tridiagonalise(LargeArgs a
         // each thread sums its rows' partials (fixed order), applies
         // y -= V z1 + W z2 and, from the same loads, the next column's
         // update by the panel's earlier vectors. sy aliases row 0 of spart
-        // and every thread reads and writes only its own rows.
+        // and every thread reads and writes only its own rows (the same rows
+        // in (5) below, so no barrier separates the two passes); the partial
+        // of tau y . v over those rows is formed on the way.
         double an[kRedRows];
+        double pv = 0.0;
 #pragma unroll
         for (int rr = 0; rr < kRedRows; ++rr) {
           const int r = tid + rr * kRedBlock;
@@ -511,13 +514,12 @@ __global__ __launch_bounds__(kRedBlock, PERCU) void k_tridiagonalise(LargeArgs a
                            : panel_correct(S + (int64_t)k0 * ld + (k + 1 + r), Wb + (k + 1 + r), ld, z1, z2, i, acc);
             }
             sy[r] = acc;
+            pv = fma(tk * acc, sv[r], pv);
           }
         }
-        __syncthreads();
         // (5) w = tau y - (tau/2)(tau y . v) v into column i of W; the next
         // column takes the term of v_k, w_k: -v w[0] - w v[0], v[0] = 1
-        double pv = 0.0;
-        for (int r = tid; r < n2; r += kRedBlock) pv = fma(tk * sy[r], sv[r], pv);
+        // (block_sum's barriers also publish sy[0])
         const double Kc = 0.5 * tk * block_sum<kRedNW>(pv, red);
         const double w0 = tk * sy[0] - Kc * sv[0];
 #pragma unroll

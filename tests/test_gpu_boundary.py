@@ -244,3 +244,29 @@ def test_xcd_queues_bit_identical(precision, gpu_lib):
     print(f"{precision}: forward {ex:.2e}, adjoint saved {e1:.2e}, recomputed {e2:.2e}", flush=True)
     assert ex <= tol and e1 <= tol and e2 <= tol
 
+
+def test_library_loaded_before_torch_uses_torch_runtime(gpu_lib):
+    """A process that loads the library and sets an option before torch
+    touches the GPU still computes correctly (the binding brings torch's HIP
+    runtime in first). Runs in a child process with a fresh interpreter."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_1710_10899_amd import _lib\n"
+        "_lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-5)\n"
+        "import numpy as np, torch\n"
+        "import oracle\n"
+        "from workloads import generators as G\n"
+        "import paper_1710_10899_amd as sm\n"
+        "c = G.banded_spd(200, 6)\n"
+        "rp, ci, va = (torch.from_numpy(v).cuda() for v in (c.rowptr, c.colind, c.vals))\n"
+        "x = sm.invroot_fwd(rp, ci, va, 2).cpu().numpy()\n"
+        "r, _ = oracle.forward(c.rowptr, c.colind, c.vals, c.n, 2)\n"
+        "print('rel', float(np.linalg.norm(x - r) / np.linalg.norm(r)))\n")
+    banner("library loaded before torch, in a child process")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240,
+                         cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1]))
+    print(out.stdout[-500:], out.stderr[-2000:], flush=True)
+    assert out.returncode == 0
+    rel = float(out.stdout.split("rel")[-1])
+    assert rel <= TOL64

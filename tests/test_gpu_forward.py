@@ -269,19 +269,20 @@ def test_near_degenerate_eigenvalues_unsplit(gpu_lib):
         assert err <= TOL64 and st["unconverged"] == 0
 
 
-@pytest.mark.parametrize("ctol", [0.0, 1e-2, 0.5])
+@pytest.mark.parametrize("ctol", [0.0, 1e-5, 1e-2, 0.5])
 def test_cluster_tolerance_paths(ctol, gpu_lib):
-    """Twisted factorisation only (0), many clusters (1e-2), every eigenvalue
-    of a block in one cluster (0.5, inverse iteration throughout): all meet
-    the FP64 bar."""
+    """Twisted factorisation only (0), the earlier default (1e-5), many
+    clusters (1e-2), every eigenvalue of a block in one cluster (0.5, inverse
+    iteration throughout): all meet the FP64 bar."""
     from paper_1710_10899_amd import _lib
     csr = G.overlap_matrix(n_atoms=24, nbf=13, rcut=4.14, kappa=100.0, seed=83)
     banner(f"cluster tolerance {ctol}")
+    default = _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL)
     _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, ctol)
     try:
         x, st = gpu_forward(csr, 2)
     finally:
-        _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-5)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, default)
     ref, _ = oracle_forward(csr, 2)
     err = rel_fro(x, ref)
     print(f"ctol={ctol} rel_err={err:.3e} status={st}", flush=True)

@@ -53,10 +53,10 @@ def test_version_strerror_options_without_gpu():
     assert _lib.submat_strerror(-3) == "diagonal entry not stored"
     assert _lib.submat_strerror(0) == "ok"
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_KAPPA_MAX) == 1e5
-    assert _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL) == 1e-5
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL) == 1e-7
     _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 0.5)
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_CLUSTER_TOL) == 0.5
-    _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-5)
+    _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1e-7)
     with pytest.raises(_lib.SubmatError):
         _lib.submat_set_option(_lib.SUBMAT_OPT_CLUSTER_TOL, 1.0)
     with pytest.raises(_lib.SubmatError):

@@ -275,13 +275,20 @@ def _pool_work(cols):
 
 def cpu_baseline(csr, w, p, n_sample=None, fn="inv_root"):
     """The FP64 oracle (forward + adjoint per column) on a seeded sample of
-    columns, one single-threaded-BLAS worker process per host core. Returns
+    columns, one single-threaded-BLAS worker process per available host core
+    (at most 16). Returns
     the line's cpu_baseline object and the oracle's forward segments of the
     sampled columns (for the accuracy check of the GPU output)."""
     import multiprocessing as mp
 
     import numpy as np
-    cores = os.cpu_count() or 1
+    # one worker per host core the process may run on, at most 16: a GPU's
+    # share of the host on the machines this runs on
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(avail, 16))
     if n_sample is None:
         # about 20 s of CPU work: 384 columns at the 6656-column workload's
         # mean m^3 on 16 cores, scaled by this workload's and the core count
@@ -311,7 +318,7 @@ def cpu_baseline(csr, w, p, n_sample=None, fn="inv_root"):
                 os.environ[k] = v
     done = len(segs)
     return {"value": done / dt, "unit": "submatrices/s", "cores": cores, "kind": "oracle",
-            "cpu_model": cpu_model(),
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "affinity_cpus": avail,
             "sample": f"{done} seeded columns of the same workload, forward + adjoint per column, "
                       f"{cores} processes with single-threaded BLAS, {dt:.2f} s wall"}, segs
 

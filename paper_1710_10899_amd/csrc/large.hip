@@ -1397,8 +1397,8 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_apply(LargeArgs
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
       const T* VT = VTs + (int64_t)k0 * ld + (k0 + 1);
       T* Qs = Q + (k0 + 1);
-      // Wm = VT^T Q_sub (nbt x nc), Q_sub -= V Wm
-      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, nc, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
+      // Wm = VT^T Q_sub (nbt x nc; one 128 x 64 tile, so Q_sub is read once), Q_sub -= V Wm
+      wg_gemm<T, kBackNW, true, false, false, 1, 4, 2>(nbt, nc, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
       wg_gemm<T, kBackNW, false, false, false, 1>(n2, nc, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
     }
   }
@@ -1692,10 +1692,10 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_product(LargeArgs 
     T* Ms = at<T>(a.S, a.off[it]);
     T* T1 = at<T>(a.W, a.off[it]);
     if (!LOWER)
-      wg_gemm<T, kAdjNW, false, false, false, 1>(m, nc, m, T(1), Q, ld, Ms + (int64_t)c0 * ld, ld, T(0),
+      wg_gemm<T, kAdjNW, false, false, false, 1, 4, 2>(m, nc, m, T(1), Q, ld, Ms + (int64_t)c0 * ld, ld, T(0),
                                                  T1 + (int64_t)c0 * ld, ld, gsm);
     else
-      wg_gemm<T, kAdjNW, false, true, true, 1>(m - c0, nc, m, T(1), T1 + c0, ld, Q + c0, ld, T(0),
+      wg_gemm<T, kAdjNW, false, true, true, 1, 4, 2>(m - c0, nc, m, T(1), T1 + c0, ld, Q + c0, ld, T(0),
                                                Ms + (int64_t)c0 * ld + c0, ld, gsm);
   }
 }
@@ -1879,9 +1879,9 @@ hipError_t launch_back_apply(const LargeArgs& a, hipStream_t s) {
   if (a.n_items <= 0) return hipSuccess;
   if ((int64_t)a.n_items * ((a.max_m + kBackCols - 1) / kBackCols) > INT32_MAX) return hipErrorInvalidValue;
   if (a.fp64)
-    hipLaunchKernelGGL(k_back_apply<double>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 8, s, a);
+    hipLaunchKernelGGL(k_back_apply<double>, dim3(a.grid), dim3(kBackBlock), (gemm_lds_elems<kBackNW, 4, 2>() * 8), s, a);
   else
-    hipLaunchKernelGGL(k_back_apply<float>, dim3(a.grid), dim3(kBackBlock), gemm_lds_elems<kBackNW>() * 4, s, a);
+    hipLaunchKernelGGL(k_back_apply<float>, dim3(a.grid), dim3(kBackBlock), (gemm_lds_elems<kBackNW, 4, 2>() * 4), s, a);
   return hipGetLastError();
 }
 
@@ -1943,14 +1943,14 @@ hipError_t launch_adjoint_product(const LargeArgs& a, int lower, hipStream_t s) 
   if ((int64_t)a.n_items * ((a.max_m + kBackCols - 1) / kBackCols) > INT32_MAX) return hipErrorInvalidValue;
   if (a.fp64) {
     if (lower)
-      hipLaunchKernelGGL((k_adj_product<double, true>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 8, s, a);
+      hipLaunchKernelGGL((k_adj_product<double, true>), dim3(a.grid), dim3(kAdjBlock), (gemm_lds_elems<kAdjNW, 4, 2>() * 8), s, a);
     else
-      hipLaunchKernelGGL((k_adj_product<double, false>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 8, s, a);
+      hipLaunchKernelGGL((k_adj_product<double, false>), dim3(a.grid), dim3(kAdjBlock), (gemm_lds_elems<kAdjNW, 4, 2>() * 8), s, a);
   } else {
     if (lower)
-      hipLaunchKernelGGL((k_adj_product<float, true>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 4, s, a);
+      hipLaunchKernelGGL((k_adj_product<float, true>), dim3(a.grid), dim3(kAdjBlock), (gemm_lds_elems<kAdjNW, 4, 2>() * 4), s, a);
     else
-      hipLaunchKernelGGL((k_adj_product<float, false>), dim3(a.grid), dim3(kAdjBlock), gemm_lds_elems<kAdjNW>() * 4, s, a);
+      hipLaunchKernelGGL((k_adj_product<float, false>), dim3(a.grid), dim3(kAdjBlock), (gemm_lds_elems<kAdjNW, 4, 2>() * 4), s, a);
   }
   return hipGetLastError();
 }

@@ -106,7 +106,7 @@ def cpu_model() -> str:
 
 def kernel_source_hash() -> str:
     """sha256 over the HIP library's sources with comments and blank space
-    removed: the counters in profiles/traffic.json stay valid across edits
+    removed: the counters in profiles/traffic_*.json stay valid across edits
     that cannot change a kernel."""
     import hashlib
     import re
@@ -153,9 +153,9 @@ def _phase_of(name: str):
     return None
 
 
-def _read_counters(path, names):
-    """{kernel: {counter: mean over dispatches of the per-dispatch sum}} from
-    a rocprofv3 counter_collection.csv."""
+def _read_counters(path, names, reduce="mean"):
+    """{kernel: {counter: mean (or max) over dispatches of the per-dispatch
+    sum}} from a rocprofv3 counter_collection.csv."""
     import csv
     import collections
     per = collections.defaultdict(lambda: collections.defaultdict(float))
@@ -167,6 +167,8 @@ def _read_counters(path, names):
     for (k, _), d in per.items():
         for c, v in d.items():
             byk[k][c].append(v)
+    if reduce == "max":
+        return {k: {c: max(v) for c, v in d.items()} for k, d in byk.items()}
     return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in byk.items()}
 
 
@@ -185,9 +187,12 @@ def summarise_profile(d: str, command: str, workload: int, precision: str) -> No
             stats[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]) / 1e6, float(r["Percentage"]))
     ctr, scale = {}, {}
     for tag, cname in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
-        byk = {k: v[cname] * 1024.0 for k, v in _read_counters(os.path.join(d, f"{tag}_counter_collection.csv"),
-                                                                 {cname}).items()}
-        probe = max((v for k, v in byk.items() if _phase_of(k) is None), default=0.0)
+        path = os.path.join(d, f"{tag}_counter_collection.csv")
+        byk = {k: v[cname] * 1024.0 for k, v in _read_counters(path, {cname}).items()}
+        # the probe is the largest single dispatch outside the library (the
+        # 1 GiB copy; other copies of the same kernel are the small inputs)
+        peak = {k: v[cname] * 1024.0 for k, v in _read_counters(path, {cname}, "max").items()}
+        probe = max((v for k, v in peak.items() if _phase_of(k) is None), default=0.0)
         scale[tag] = (1 << 30) / probe if probe > 0 else float("nan")
         ctr[tag] = {k: scale[tag] * v for k, v in byk.items()}
     dram, flops = {}, {}

@@ -295,10 +295,11 @@ def cpu_baseline(csr, w, p, n_sample=None, fn="inv_root"):
         avail = os.cpu_count() or 1
     cores = max(1, min(avail, 16))
     if n_sample is None:
-        # about 20 s of CPU work: 384 columns at the 6656-column workload's
-        # mean m^3 on 16 cores, scaled by this workload's and the core count
+        # about 10 s of wall time (~160 core-seconds): ~4900 columns at the
+        # 6656-column workload's mean m^3 on 16 cores (about 32 ms per column
+        # and core, measured), scaled by this workload's and the core count
         m3 = float((csr.row_sizes().astype(np.float64) ** 3).mean())
-        n_sample = int(max(32, min(csr.n, 24 * cores * 6.9e7 / m3)))
+        n_sample = int(max(32, min(csr.n, 300 * cores * 6.9e7 / m3)))
     rng = np.random.default_rng(171010899 + 400)
     cols = np.sort(rng.choice(csr.n, min(n_sample, csr.n), replace=False))
     chunks = [cols[i::cores * 4].tolist() for i in range(cores * 4)]

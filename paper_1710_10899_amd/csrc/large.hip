@@ -1142,13 +1142,21 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
       const bool hasP = j0 > 0;
       if (tid < kOrthB) bsc[tid] = tid < nb ? zsc[j0 + tid] : 0.0;
       const double lsc = li < nb ? zsc[j0 + li] : 0.0;
-      // pass 1: wave w takes rows 4w.., 4(w+NW).. (four rows per MFMA step)
+      // pass 1: wave w takes rows 4w.., 4(w+NW).. (four rows per MFMA step).
+      // Loads are unconditional (rows past m read row m - 1, columns past nb
+      // lie in the slab's padding, ld being a multiple of 16; without a
+      // previous block P reads B) and masked afterwards, so that the
+      // unrolled steps keep several loads in flight.
       acc_t cacc = acc_t{0, 0, 0, 0}, hacc = acc_t{0, 0, 0, 0};
+      const double* Pr = hasP ? P : B;
+#pragma unroll 4
       for (int i0 = 4 * wv; i0 < m; i0 += 4 * kEigNW) {
         const int i = i0 + lk;
+        const int64_t o = (int64_t)(i < m ? i : m - 1) * ld + li;
+        const double braw = B[o], praw = Pr[o];
         const bool ok = i < m && li < nb;
-        const double bv = ok ? B[(int64_t)i * ld + li] * lsc : 0.0;
-        const double pv = (hasP && i < m) ? P[(int64_t)i * ld + li] : 0.0;
+        const double bv = ok ? braw * lsc : 0.0;
+        const double pv = (hasP && i < m) ? praw : 0.0;
         hacc = Mfma<double>::step(bv, bv, hacc);
         cacc = Mfma<double>::step(pv, bv, cacc);
       }

@@ -1149,16 +1149,25 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
       // unrolled steps keep several loads in flight.
       acc_t cacc = acc_t{0, 0, 0, 0}, hacc = acc_t{0, 0, 0, 0};
       const double* Pr = hasP ? P : B;
-#pragma unroll 4
-      for (int i0 = 4 * wv; i0 < m; i0 += 4 * kEigNW) {
-        const int i = i0 + lk;
-        const int64_t o = (int64_t)(i < m ? i : m - 1) * ld + li;
-        const double braw = B[o], praw = Pr[o];
-        const bool ok = i < m && li < nb;
-        const double bv = ok ? braw * lsc : 0.0;
-        const double pv = (hasP && i < m) ? praw : 0.0;
-        hacc = Mfma<double>::step(bv, bv, hacc);
-        cacc = Mfma<double>::step(pv, bv, cacc);
+      constexpr int kU = 4;  // MFMA steps whose loads are issued together
+      for (int i00 = 4 * wv; i00 < m; i00 += 4 * kEigNW * kU) {
+        double braw[kU], praw[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i00 + 4 * kEigNW * u + lk;
+          const int64_t o = (int64_t)(i < m ? i : m - 1) * ld + li;
+          braw[u] = B[o];
+          praw[u] = Pr[o];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int i = i00 + 4 * kEigNW * u + lk;
+          const bool ok = i < m && li < nb;
+          const double bv = ok ? braw[u] * lsc : 0.0;
+          const double pv = (hasP && i < m) ? praw[u] : 0.0;
+          hacc = Mfma<double>::step(bv, bv, hacc);
+          cacc = Mfma<double>::step(pv, bv, cacc);
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1217,20 +1226,35 @@ __global__ __launch_bounds__(kEigBlock) void k_eig_orth(LargeArgs a) {
       // writes it. The columns go to Q (column-major) through an LDS
       // transpose so that both the reads and the writes coalesce.
       for (int i0 = 0; i0 < m; i0 += kWave) {
+        // (each row's 16 values loaded together and unconditionally: rows past
+        // m read row m - 1 and are discarded, columns past nb lie in the
+        // padding and are masked)
         for (int q = tid; q < kWave * kOrthB; q += kEigBlock) {
           const int ii = q / kOrthB, lq = q - ii * kOrthB, i = i0 + ii;
+          const int64_t o = (int64_t)(i < m ? i : m - 1) * ld;
+          constexpr int kH = kOrthB / 2;  // values in flight per batch
+          double bv[kH];
           double v = 0.0;
-          if (i < m) {
-            double bv[kOrthB];
 #pragma unroll
-            for (int kk = 0; kk < kOrthB; ++kk) bv[kk] = kk < nb ? B[(int64_t)i * ld + kk] : 0.0;
+          for (int h = 0; h < kOrthB; h += kH) {
 #pragma unroll
-            for (int kk = 0; kk < kOrthB; ++kk) v = fma(bv[kk], Ri[kk * kOrthB + lq], v);
-            if (hasP) {
+            for (int kk = 0; kk < kH; ++kk) bv[kk] = B[o + h + kk];
 #pragma unroll
-              for (int kk = 0; kk < kOrthB; ++kk) v = fma(-P[(int64_t)i * ld + kk], Ds[kk * kOrthB + lq], v);
+            for (int kk = 0; kk < kH; ++kk) v = fma(h + kk < nb ? bv[kk] : 0.0, Ri[(h + kk) * kOrthB + lq], v);
+          }
+          if (hasP) {
+#pragma unroll
+            for (int h = 0; h < kOrthB; h += kH) {
+#pragma unroll
+              for (int kk = 0; kk < kH; ++kk) bv[kk] = P[o + h + kk];
+#pragma unroll
+              for (int kk = 0; kk < kH; ++kk) v = fma(-bv[kk], Ds[(h + kk) * kOrthB + lq], v);
             }
+          }
+          if (i < m) {
             if (lq < nb) B[(int64_t)i * ld + lq] = v;
+          } else {
+            v = 0.0;
           }
           tile[lq * (kWave + 1) + ii] = v;
         }
@@ -1650,9 +1674,24 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_prep(LargeArgs a) 
       alv[i] = spec_node((double)lam[i], a.fn);
     }
     __syncthreads();
+    // a = Q^T w, a wave per column of Q; four row groups' loads issued
+    // together (unconditional: rows past m read row m - 1, masked)
     for (int pc = wv; pc < m; pc += kAdjNW) {
+      const T* qc = Q + (int64_t)pc * ld;
       double part = 0.0;
-      for (int r = lane; r < m; r += kWave) part = fma((double)Q[(int64_t)pc * ld + r], w[r], part);
+      for (int r0 = lane; r0 < m; r0 += 4 * kWave) {
+        double qv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + u * kWave;
+          qv[u] = (double)qc[r < m ? r : m - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + u * kWave;
+          if (r < m) part = fma(qv[u], w[r], part);
+        }
+      }
       part = wave_sum(part);
       if (lane == 0) av[pc] = part;
     }

@@ -1783,14 +1783,27 @@ __global__ __launch_bounds__(kAdjBlock, kAdjPerCU) void k_adj_scatter(LargeArgs 
     for (int k = wv; k < m; k += kAdjNW) {
       const int r = R[k];
       const int s0 = a.rowptr[r], s1 = a.rowptr[r + 1];
-      for (int q = s0 + lane; q < s1; q += kWave) {
-        const int cq = a.colind[q];
-        if (cq > r) break;
-        const int l = find_sorted(R, m, cq);
-        if (l >= 0) {
-          const int hi = l > k ? l : k, lo = l > k ? k : l;
-          atomicAdd(&ga[q], bad ? (VT)NAN : (VT)Ms[(int64_t)lo * ld + hi]);
+      // four entries per lane and step, their column indices loaded together
+      // (entries past the row's end read its last one and are skipped)
+      for (int q0 = s0 + lane; q0 < s1; q0 += 4 * kWave) {
+        int cq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * kWave;
+          cq[u] = a.colind[q < s1 ? q : s1 - 1];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int q = q0 + u * kWave;
+          if (q < s1 && cq[u] <= r) {
+            const int l = find_sorted(R, m, cq[u]);
+            if (l >= 0) {
+              const int hi = l > k ? l : k, lo = l > k ? k : l;
+              atomicAdd(&ga[q], bad ? (VT)NAN : (VT)Ms[(int64_t)lo * ld + hi]);
+            }
+          }
+        }
+        if (cq[3] > r) break;  // the row is sorted: the rest lies above the diagonal
       }
     }
     if (tid == 0) atomicAdd((unsigned long long*)&a.status[ST_DONE], 1ull);

@@ -194,7 +194,7 @@ __device__ __forceinline__ void panel_strip_dots(const T* __restrict__ P, int ld
   for (int r = nl + lane; r - lane < n; r += 2 * kWave) {
     const int r2 = r + kWave;
     const bool in = r < n, in2 = r2 < n;
-    const uint32_t ra = in ? r : 0, rb = in2 ? r2 : 0;
+    const uint32_t ra = in ? r : n - 1, rb = in2 ? r2 : n - 1;  // past the end: the last row (see the symv)
     double av[kStrip], aw[kStrip];
 #pragma unroll
     for (int u = 0; u < kStrip; ++u) {
@@ -255,11 +255,11 @@ __device__ void symv_lower_strips(const T* __restrict__ A, int ld, int n, const 
       bool in[RG];
 #pragma unroll
       for (int g = 0; g < RG; ++g) {
-        // unconditional loads (rows past the end read row 0 of a valid
-        // column, columns past the end read column c0) and masked values:
-        // no branch per load
+        // unconditional loads (rows past the end read the column's last row,
+        // whose cache line the in-range lanes fetch anyway; columns past the
+        // end read column c0) and masked values: no branch per load
         in[g] = r + g * kWave < n;
-        const uint32_t rg = in[g] ? r + g * kWave : 0;
+        const uint32_t rg = in[g] ? r + g * kWave : n - 1;
 #pragma unroll
         for (int u = 0; u < kStrip; ++u) av[g][u] = (double)A[(uint32_t)col[u] + rg];
       }

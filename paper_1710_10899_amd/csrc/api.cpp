@@ -1420,7 +1420,7 @@ int submat_pcg(const int32_t* rowptr, const int32_t* colind, const double* a_val
                   (hipStream_t)stream);
 }
 
-int32_t submat_version(void) { return 130; }
+int32_t submat_version(void) { return 131; }
 
 int submat_time_phases(const int32_t* rowptr, const int32_t* colind, const void* vals, int32_t n, int64_t nnz,
                        int32_t fn, double param, int32_t dtype, int32_t precision, void* x_vals,

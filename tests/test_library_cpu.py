@@ -49,7 +49,7 @@ def test_binding_covers_header():
 def test_version_strerror_options_without_gpu():
     from paper_1710_10899_amd import _lib
     _lib.load()
-    assert _lib.submat_version() == 130
+    assert _lib.submat_version() == 131
     assert _lib.submat_strerror(-3) == "diagonal entry not stored"
     assert _lib.submat_strerror(0) == "ok"
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_KAPPA_MAX) == 1e5

@@ -61,7 +61,7 @@ def flops_model(m):
     return float(((10.0 / 3.0) * m ** 3 + 3 * m ** 2).sum()), float((3.0 * m ** 3 + 5 * m ** 2).sum())
 
 
-def phase_work(m, phase, elt=8, small_max=64):
+def phase_work(m, phase, elt=8, small_max=32):
     """Algorithmic work of a phase summed over one step's launches of it
     (all columns of its bucket): (amount, unit, bound). Flop counts are those
     of the benchmark model above; the reduction, the back-transformation and
@@ -86,7 +86,7 @@ def phase_work(m, phase, elt=8, small_max=64):
     return None, None, None
 
 
-def reduction_bytes(m, elt=8, small_max=64):
+def reduction_bytes(m, elt=8, small_max=32):
     """The reduction's compulsory stream: the lower triangle of the trailing
     matrix once per column, sum_k elt (m-k)^2 / 2 ~ (elt/6) m^3 bytes."""
     big = m[m > small_max].astype("float64")
@@ -340,8 +340,9 @@ def plain_path(sm, _lib, rp, ci, va, gx, fn, param, m, n_sample=96):
     n = m.size
     stride = max(1, n // n_sample)
     order = np.argsort(-m, kind="stable")
-    small = order[m[order] <= 64]
-    large = order[m[order] > 64]
+    edge = int(_lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX))  # the library's bucket edge
+    small = order[m[order] <= edge]
+    large = order[m[order] > edge]
     picked = np.concatenate([small[::stride], large[::stride]])
     _lib.submat_set_option(_lib.SUBMAT_OPT_PLAIN_STRIDE, stride)
     try:
@@ -780,6 +781,7 @@ def run_step(args, np, torch, sm, _lib, G):
         "status": st,
     }
 
+    edge = int(_lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX))  # one-wavefront bucket edge
     if not args.no_phases:
         # per-phase device time of one forward + adjoint (direct launches,
         # HIP events on the library's stream = torch's current stream)
@@ -790,7 +792,7 @@ def run_step(args, np, torch, sm, _lib, G):
         for k, (ms, nl) in ph.items():
             if not nl:
                 continue
-            amount, unit, bound = phase_work(m, k, elt)
+            amount, unit, bound = phase_work(m, k, elt, edge)
             row = {"ms_per_launch": round(ms / nl, 3), "launches": nl, "ms_total": round(ms, 3)}
             if amount is not None:
                 # passes over the columns: the forward's, plus the adjoint's
@@ -816,7 +818,7 @@ def run_step(args, np, torch, sm, _lib, G):
                                "executed_tflop_per_launch": (meas["executed_flop"] / 1e12
                                                              if meas and meas.get("executed_flop") else None)}
             if dom == "tridiagonalise":
-                gb = d["achieved"] * 1e12 * reduction_bytes(m, elt) / phase_work(m, dom, elt)[0] / 1e9
+                gb = d["achieved"] * 1e12 * reduction_bytes(m, elt, edge) / phase_work(m, dom, elt, edge)[0] / 1e9
                 out["roofline"]["bytes_view"] = {"achieved": gb, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                                  "frac": gb / HBM_PEAK_GBS,
                                                  "note": "lower triangle of the trailing matrix streamed once "

@@ -102,17 +102,21 @@ extern "C" {
 #define SUBMAT_OPT_KAPPA_MAX 1   /* FP64-fallback threshold on lambda_max/lambda_min (1e5) */
 #define SUBMAT_OPT_USE_GRAPH 2   /* 1: capture each call sequence once in a hipGraph and
                                     replay it (default 1); 0: direct launches */
-#define SUBMAT_OPT_SMALL_MAX 3   /* largest order on the one-wavefront Jacobi path (64) */
+#define SUBMAT_OPT_SMALL_MAX 3   /* largest order on the one-wavefront Jacobi path, 1..64;
+                                    0 (the initial state): the tuning table's (64 built in);
+                                    setting it, or a table change that moves it, drops
+                                    cached plans */
 #define SUBMAT_OPT_WS_BYTES 4    /* workspace budget per plan in bytes (0: automatic) */
 #define SUBMAT_OPT_CLUSTER_TOL 5 /* relative eigenvalue gap (times ||T||) below which the
                                     tridiagonal eigensolver computes eigenvectors by inverse
                                     iteration with reorthogonalisation (1e-7), in [0, 1) */
-#define SUBMAT_OPT_TUNE_FILE 6   /* tuning table of workgroups per compute unit: set 1 to
+#define SUBMAT_OPT_TUNE_FILE 6   /* tuning table (workgroups per compute unit, the reduction's
+                                    panel width, the one-wavefront bucket edge): set 1 to
                                     (re)read the file named by the environment variable
-                                    SUBMAT_TUNE_FILE (lines "kind m_hi blocks_per_cu", as
-                                    written by the package's autotune module), 0 for the
-                                    built-in table; get returns 1 when a file is in use.
-                                    The table is first read at the first call. */
+                                    SUBMAT_TUNE_FILE (lines "kind m_hi value", as written
+                                    by the package's autotune module), 0 for the built-in
+                                    table; get returns 1 when a file is in use. The table is
+                                    first read at the first call. */
 #define SUBMAT_OPT_DETERMINISTIC 7 /* 1: the adjoint is assembled without atomic adds: each
                                     phase (the one-wavefront launch, each chunk of the
                                     large-order path) leaves every D_j in memory, then every

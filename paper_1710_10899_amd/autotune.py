@@ -5,10 +5,13 @@ persistent kernels by timing the library's own phases on seeded
 overlap-type workloads whose orders fall in each range: workgroups per
 compute unit of the FP64 and FP32 dense stages and of the tridiagonal
 eigensolver, and the panel width and workgroups per compute unit of the
-tridiagonal reduction (FP64 and FP32). The result is a table file with
-lines "kind m_hi value" (kind 0 / 1 = FP32 / FP64 dense kernels, 2 =
-tridiagonal eigensolver, 3 / 4 = FP64 / FP32 reduction panel width, 5 / 6
-= FP64 / FP32 reduction workgroups per compute unit); point the
+tridiagonal reduction (FP64 and FP32), and the edge between the
+one-wavefront Jacobi bucket and the reduction path (timed on a workload of
+orders on both sides of it). The result is a table file with lines "kind
+m_hi value" (kind 0 / 1 = FP32 / FP64 dense kernels, 2 = tridiagonal
+eigensolver, 3 / 4 = FP64 / FP32 reduction panel width, 5 / 6 = FP64 / FP32
+reduction workgroups per compute unit, 7 = largest order of the
+one-wavefront bucket); point the
 environment variable SUBMAT_TUNE_FILE at it (the library reads it at its
 first call, or when submat_set_option(SUBMAT_OPT_TUNE_FILE, 1) is called).
 
@@ -31,7 +34,11 @@ import time
 DEFAULTS = [(1, 128, 8), (1, 256, 4), (1, 1024, 2), (1, 1 << 30, 1),
             (0, 128, 8), (0, 256, 4), (0, 1024, 2), (0, 1 << 30, 1),
             (2, 256, 8), (2, 512, 6), (2, 1024, 4), (2, 1 << 30, 1),
-            (3, 1 << 30, 16), (4, 1 << 30, 16), (5, 1 << 30, 2), (6, 1 << 30, 3)]
+            (3, 1 << 30, 16), (4, 1 << 30, 16), (5, 1 << 30, 2), (6, 1 << 30, 3),
+            (7, 1 << 30, 32)]
+# one-wavefront bucket edges tried (orders above go to the reduction path)
+EDGE_CANDIDATES = (32, 40, 48, 56, 64)
+EDGE_WORKLOAD_MAX_ORDER = 96
 # reduction candidates: (panel width, workgroups per compute unit)
 REDUCTION_CANDIDATES = ((8, 2), (16, 2), (24, 2), (32, 2), (16, 1), (32, 1), (16, 3), (24, 3), (16, 4))
 BUCKETS = (128, 256, 512, 1024)
@@ -78,7 +85,7 @@ def time_phases(csr, precision, phases, reps):
     best = math.inf
     for _ in range(reps):
         ph = api.time_phases(rp, ci, va, 2, precision, grad_x=gx, fn="inv_root")
-        best = min(best, sum(ph[k][0] for k in phases if k in ph))
+        best = min(best, sum(ph[k][0] for k in (phases if phases is not None else ph) if k in ph))
     return best
 
 
@@ -134,6 +141,20 @@ def main(argv=None):
                 print(f"[autotune]   reduction {precision}: " + ", ".join(f"nb={a} x{b}:{v:.2f}ms"
                                                                      for (a, b), v in res.items())
                       + f" -> nb={nb} x{pc}", flush=True)
+        # the bucket edge: forward + adjoint over every phase of a workload
+        # whose orders straddle the candidates
+        csr = workload_for(EDGE_WORKLOAD_MAX_ORDER, args.atoms, seed=171010899 + 590)
+        m = csr.row_sizes()
+        print(f"[autotune] bucket edge: n={csr.n} m {m.min()}..{m.max()}", flush=True)
+        res = {}
+        for e in (EDGE_CANDIDATES if not args.quick else (48, 64)):
+            write_table(tmp, table_with(table, 7, 1 << 30, e))
+            _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+            res[e] = time_phases(csr, "f64", None, args.reps)
+        edge = min(res, key=res.get)
+        table = table_with(table, 7, 1 << 30, edge)
+        print("[autotune]   edge: " + ", ".join(f"{e}:{v:.2f}ms" for e, v in res.items()) + f" -> {edge}",
+              flush=True)
     finally:
         if old_env is None:
             os.environ.pop("SUBMAT_TUNE_FILE", None)

@@ -28,7 +28,7 @@ namespace {
 struct Options {
   double kappa_max = 1e5;
   int use_graph = 1;
-  int small_max = 64;
+  int small_max = 0;       // one-wavefront bucket edge set by the caller (0: the tuning table's)
   double ws_bytes = 0.0;
   double cluster_tol = 1e-7;
   int deterministic = 0;   // adjoint assembled in a fixed order instead of by atomic adds
@@ -296,7 +296,7 @@ int build_plan_once(const int32_t* rowptr, const int32_t* colind, int32_t n, int
   P.colind = colind;
   P.n = n;
   P.nnz = nnz;
-  P.small_max = std::min(64, std::max(1, g_opt.small_max));
+  P.small_max = std::min(64, std::max(1, g_opt.small_max > 0 ? g_opt.small_max : tuned_small_max()));
   int rc;
   if ((rc = P.d_m.alloc(n)) || (rc = P.d_c.alloc(n))) return rc;
   DevBuf<uint32_t> err;
@@ -1281,8 +1281,8 @@ int submat_set_option(int32_t key, double value) {
       g_opt.use_graph = value != 0.0;
       return SUBMAT_OK;
     case SUBMAT_OPT_SMALL_MAX:
-      if (value < 1 || value > 64) return SUBMAT_EINVAL;
-      g_opt.small_max = (int)value;
+      if (value < 0 || value > 64 || value != std::floor(value)) return SUBMAT_EINVAL;
+      g_opt.small_max = (int)value;  // 0: the tuning table's edge
       g_plans.clear();
       g_saved.clear();
       return SUBMAT_OK;
@@ -1296,11 +1296,18 @@ int submat_set_option(int32_t key, double value) {
       if (!(value >= 0.0 && value < 1.0)) return SUBMAT_EINVAL;
       g_opt.cluster_tol = value;
       return SUBMAT_OK;
-    case SUBMAT_OPT_TUNE_FILE:
+    case SUBMAT_OPT_TUNE_FILE: {
       if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
+      const int edge = tuned_small_max();
       reload_tuning(value == 1.0);
       g_opt.tune_gen++;
+      if (g_opt.small_max == 0 && tuned_small_max() != edge) {
+        // the bucket edge is part of every plan
+        g_plans.clear();
+        g_saved.clear();
+      }
       return SUBMAT_OK;
+    }
     case SUBMAT_OPT_DETERMINISTIC:
       if (value != 0.0 && value != 1.0) return SUBMAT_EINVAL;
       g_opt.deterministic = (int)value;
@@ -1323,7 +1330,7 @@ double submat_get_option(int32_t key) {
   switch (key) {
     case SUBMAT_OPT_KAPPA_MAX: return g_opt.kappa_max;
     case SUBMAT_OPT_USE_GRAPH: return g_opt.use_graph;
-    case SUBMAT_OPT_SMALL_MAX: return g_opt.small_max;
+    case SUBMAT_OPT_SMALL_MAX: return g_opt.small_max > 0 ? g_opt.small_max : tuned_small_max();
     case SUBMAT_OPT_WS_BYTES: return g_opt.ws_bytes;
     case SUBMAT_OPT_CLUSTER_TOL: return g_opt.cluster_tol;
     case SUBMAT_OPT_TUNE_FILE: return tuning_from_file() ? 1.0 : 0.0;

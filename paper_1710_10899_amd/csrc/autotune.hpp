@@ -16,6 +16,9 @@ int tuned_eig_blocks_per_cu(int max_m);
 int tuned_reduction_nb(int max_m, int fp64);
 int tuned_reduction_per_cu(int max_m, int fp64);
 
+// Largest order of the one-wavefront (Jacobi) bucket, 1..64.
+int tuned_small_max();
+
 // Reloads the table: from the file named by SUBMAT_TUNE_FILE when use_file
 // (built-in defaults when unset, unreadable or empty), else the defaults.
 void reload_tuning(bool use_file);

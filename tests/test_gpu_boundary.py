@@ -199,7 +199,7 @@ def test_every_column_processed_exactly_once(small_max, gpu_lib):
     finally:
         _lib.submat_set_option(_lib.SUBMAT_OPT_KAPPA_MAX, 1e5)
         _lib.submat_set_option(_lib.SUBMAT_OPT_WS_BYTES, 0.0)
-        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 64)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 0)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32_mixed"])

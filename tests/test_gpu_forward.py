@@ -309,3 +309,36 @@ def test_results_independent_of_launch_grid(gpu_lib, tmp_path, monkeypatch):
     finally:
         _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 0)
     assert np.array_equal(x, ref)
+
+
+def test_bucket_edge_from_tuning_table(gpu_lib, tmp_path, monkeypatch):
+    """The one-wavefront bucket edge comes from the tuning table (kind 7):
+    with edge 40 the orders 50 and 64 run on the reduction path (its phases
+    launch), with the built-in 64 they do not; both equal the oracle."""
+    import torch
+    import paper_1710_10899_amd as sm
+    from paper_1710_10899_amd import _lib
+    from paper_1710_10899_amd import autotune
+    csr = G.block_diagonal_spd((1, 7, 30, 50, 64), kappa=40.0, permute=True)
+    ref, _ = oracle_forward(csr, 2)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("SUBMAT_TUNE_FILE", str(path))
+    rp, ci, va = to_dev(csr)
+    try:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 0)  # the table's edge
+        for edge in (40, 64):
+            autotune.write_table(path, autotune.table_with(autotune.DEFAULTS, 7, 1 << 30, edge))
+            _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+            assert _lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX) == edge
+            banner(f"bucket edge {edge} from the tuning table")
+            x = torch.empty_like(va)
+            ph = sm.time_phases(rp, ci, va, 2, "f64")
+            sm.invroot_fwd(rp, ci, va, 2, "f64", out=x)
+            err = rel_fro(x.cpu().numpy(), ref)
+            large = ph.get("tridiagonalise", (0.0, 0))[1]
+            print(f"edge {edge}: reduction launches {large}, rel_err {err:.2e}", flush=True)
+            assert err <= TOL64
+            assert (large > 0) == (edge == 40)
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 0)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 0)

@@ -128,6 +128,33 @@ def test_tuning_table_option(tmp_path, monkeypatch):
     assert _lib.submat_get_option(_lib.SUBMAT_OPT_TUNE_FILE) == 0.0
 
 
+def test_bucket_edge_from_table_unless_set(tmp_path, monkeypatch):
+    """The one-wavefront bucket edge is the tuning table's (kind 7, 32
+    built in) until SUBMAT_OPT_SMALL_MAX is set; rows outside 1..64 are
+    ignored."""
+    from paper_1710_10899_amd import _lib
+    from paper_1710_10899_amd import autotune
+    _lib.load()
+    assert (7, 1 << 30, 32) in autotune.DEFAULTS
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("SUBMAT_TUNE_FILE", str(path))
+    try:
+        for edge, expect in ((48, 48), (65, 32), (0, 32)):
+            autotune.write_table(path, autotune.table_with(autotune.DEFAULTS, 7, 1 << 30, edge)
+                                 if edge != 65 and edge != 0 else
+                                 [r for r in autotune.DEFAULTS if r[0] != 7] + [(7, 1 << 30, edge)])
+            _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 1)
+            assert _lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX) == expect, edge
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 20)
+        assert _lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX) == 20
+        with pytest.raises(_lib.SubmatError):
+            _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 65)
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 0)
+        _lib.submat_set_option(_lib.SUBMAT_OPT_TUNE_FILE, 0)
+    assert _lib.submat_get_option(_lib.SUBMAT_OPT_SMALL_MAX) == 32
+
+
 def test_deterministic_option_and_release_pattern_without_gpu():
     from paper_1710_10899_amd import _lib
     _lib.load()

@@ -30,9 +30,16 @@ def _noalloc(csr, p, precision, dtype=None):
 
 
 def _planned(csr, p, precision, dtype=None):
+    """The planned entry point with every order up to 64 on the one-wavefront
+    kernel, the one the entry point that allocates nothing runs."""
     import paper_1710_10899_amd as sm
+    from paper_1710_10899_amd import _lib
     rp, ci, va = to_dev(csr, dtype)
-    return sm.invroot_fwd(rp, ci, va, p, precision).double().cpu().numpy()
+    _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 64)
+    try:
+        return sm.invroot_fwd(rp, ci, va, p, precision).double().cpu().numpy()
+    finally:
+        _lib.submat_set_option(_lib.SUBMAT_OPT_SMALL_MAX, 0)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32_mixed"])

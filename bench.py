@@ -667,8 +667,8 @@ def main():
         summarise_profile(args.summarise_profile, args.profile_command, args.workload, args.precision)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(the multi-GPU sharding is a design only)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 "
+                          "(sharding the columns over several GPUs is not implemented)"}))
         sys.exit(2)
 
     import numpy as np

@@ -26,7 +26,7 @@ Approximate Calculation of Inverse p-th Roots of Large Sparse Matrices"):
 * Section 3.4: X has exactly A's pattern; in CSR/CSC its value array is the
   concatenation of those columns and the index arrays are A's.
 
-Readings taken where the paper is silent (each is repeated in the design doc):
+Readings taken where the paper is silent:
 
 1. R_j is the *stored* pattern of column j (explicit zeros are kept), so X's
    pattern is A's pattern bit for bit (Section 3.4).

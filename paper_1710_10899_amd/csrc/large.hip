@@ -1317,7 +1317,9 @@ __device__ void wy_factor_half(const T* Gm, T* Tm, const T* tau, int c0, int nh,
   const int tid = threadIdx.x;
   for (int q = tid; q < kNBh * kNBh; q += kBackBlock) {
     const int c = q / kNBh, r = q - c * kNBh;
-    Ts[q] = (r < nh && c < nh) ? (double)Gm[(int64_t)(c0 + c) * kNBq + (c0 + r)] : 0.0;  // Ts[c*kNBh + r]
+    // Ts[c*kNBh + r] = G(c0 + r, c0 + c) for r <= c (the only entries read
+    // below), from G's lower triangle: G(c0 + c, c0 + r)
+    Ts[q] = (r < nh && c < nh && r <= c) ? (double)Gm[(int64_t)(c0 + r) * kNBq + (c0 + c)] : 0.0;
   }
   __syncthreads();
   // column by column, in place over G: column c of G (rows < c) is read
@@ -1373,16 +1375,17 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_prep(LargeArgs 
       const int n2 = m - k0 - 1;
       const int nh1 = nbt < kNBh ? nbt : kNBh, nh2 = nbt - nh1;
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
-      wg_gemm<T, kBackNW, true, false, false, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
+      // G = V^T V, lower tiles only (G is symmetric)
+      wg_gemm<T, kBackNW, true, false, true, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
       for (int q = tid; q < kNBq * kNBq; q += kBackBlock) Tm[q] = T(0);
       __syncthreads();
       wy_factor_half<T>(Gm, Tm, tau + k0, 0, nh1, Ts);
       if (nh2 > 0) {
         wy_factor_half<T>(Gm, Tm, tau + k0, kNBh, nh2, Ts);
         // T12 = -T1 (G12 T2): X = G12 T2, then T12 = -T1 X
-        const T* G12 = Gm + (int64_t)kNBh * kNBq;                  // rows 0.., columns kNBh..
+        const T* G21 = Gm + kNBh;  // rows kNBh.., columns 0..: G12 = G21^T
         const T* T22 = Tm + (int64_t)kNBh * kNBq + kNBh;
-        wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh2, T(1), G12, kNBq, T22, kNBq, T(0), Xm, kNBh, gsm);
+        wg_gemm<T, kBackNW, true, false, false, 1>(nh1, nh2, nh2, T(1), G21, kNBq, T22, kNBq, T(0), Xm, kNBh, gsm);
         wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
                                                    Tm + (int64_t)kNBh * kNBq, kNBq, gsm);
       }

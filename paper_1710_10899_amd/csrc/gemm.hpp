@@ -70,10 +70,18 @@ template <int NW, int TM = 2, int TN = 2> constexpr int gemm_lds_elems() {
 // PF: k-tiles fetched ahead into registers while the current one is
 // multiplied (0, 1 or 2; each costs 6-8 registers). Two tiles in flight
 // cover the HBM latency, which exceeds the MFMA time of one 16-deep k-tile.
-template <class T, int NW, bool TA, bool TB, bool LOWER = false, int PF = 1, int TM = 2, int TN = 2>
+// ZA, ZB: triangles of the operands that hold zeros in memory (the caller
+// guarantees it), whose products are skipped; the result is unchanged:
+//   ZA = 1: op(A)[i][k] = 0 for k < i;  ZA = 2: op(A)[i][k] = 0 for k > i;
+//   ZB = 1: op(B)[k][j] = 0 for k < j.
+// A tile's k-range is cut to the k that can meet a nonzero, and a wave's
+// 16 x 16 block skips the 4-deep k-slices that meet only zeros.
+template <class T, int NW, bool TA, bool TB, bool LOWER = false, int PF = 1, int TM = 2, int TN = 2, int ZA = 0,
+          int ZB = 0>
 __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, int lda,
                         const T* __restrict__ B, int ldb, T beta, T* __restrict__ C, int ldc, T* smem) {
   static_assert(PF >= 0 && PF <= 2, "prefetch depth 0..2");
+  static_assert(ZA >= 0 && ZA <= 2 && ZB >= 0 && ZB <= 1, "zero-triangle modes");
   constexpr int BM = 32 * TM, BK = kGemmBK, BN = 8 * NW * TN, NT = NW * kWave;
   constexpr int WM = 16 * TM, WN = 16 * TN;  // one wave's block of C
   constexpr int AL = BM * BK / NT, BL = BN * BK / NT;  // tile elements per thread
@@ -123,6 +131,13 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+      // k-range [kb, ke) of this tile: outside it every product meets a zero
+      // of the operands' triangles (kb stays a multiple of BK)
+      int kb = 0, ke = K;
+      if (ZA == 1) kb = i0;
+      if (ZB == 1 && j0 > kb) kb = j0;
+      kb = kb / BK * BK;
+      if (ZA == 2 && i0 + BM < ke) ke = i0 + BM;
       T ra[NS][AL], rb[NS][BL];
       auto fetch = [&](int slot, int k0) {
 #pragma unroll
@@ -158,7 +173,7 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
           b_at(kq, jq) = rb[slot][e];
         }
         __syncthreads();
-        if (PF > 0 && k0 + PF * BK < K) fetch(slot, k0 + PF * BK);
+        if (PF > 0 && k0 + PF * BK < ke) fetch(slot, k0 + PF * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
           T av[TM], bv[TN];
@@ -166,22 +181,28 @@ __device__ void wg_gemm(int M, int N, int K, T alpha, const T* __restrict__ A, i
           for (int a = 0; a < TM; ++a) av[a] = a_at(kk + lk, wr * WM + a * 16 + li);
 #pragma unroll
           for (int b = 0; b < TN; ++b) bv[b] = b_at(kk + lk, wc * WN + b * 16 + li);
+          const int ks = k0 + kk;  // this slice: k in [ks, ks + 4)
 #pragma unroll
-          for (int a = 0; a < TM; ++a)
+          for (int a = 0; a < TM; ++a) {
 #pragma unroll
-            for (int b = 0; b < TN; ++b)
-              if (live[a][b]) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+            for (int b = 0; b < TN; ++b) {
+              // wave-uniform: the slice meets only zeros of A's or B's triangle
+              const int r0 = i0 + wr * WM + a * 16, c0 = j0 + wc * WN + b * 16;
+              const bool zero = (ZA == 1 && ks + 4 <= r0) || (ZA == 2 && ks > r0 + 15) || (ZB == 1 && ks + 4 <= c0);
+              if (live[a][b] && !zero) acc[a][b] = Mfma<T>::step(av[a], bv[b], acc[a][b]);
+            }
+          }
         }
       };
-      if (PF >= 1) fetch(0, 0);
-      if (PF >= 2 && BK < K) fetch(NS - 1, BK);
+      if (PF >= 1 && kb < ke) fetch(0, kb);
+      if (PF >= 2 && kb + BK < ke) fetch(NS - 1, kb + BK);
       if (PF >= 2) {
-        for (int k0 = 0; k0 < K; k0 += 2 * BK) {
+        for (int k0 = kb; k0 < ke; k0 += 2 * BK) {
           step(0, k0);
-          if (k0 + BK < K) step(NS - 1, k0 + BK);
+          if (k0 + BK < ke) step(NS - 1, k0 + BK);
         }
       } else {
-        for (int k0 = 0; k0 < K; k0 += BK) step(0, k0);
+        for (int k0 = kb; k0 < ke; k0 += BK) step(0, k0);
       }
       // epilogue
 #pragma unroll

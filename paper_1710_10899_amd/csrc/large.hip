@@ -1375,8 +1375,9 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_prep(LargeArgs 
       const int n2 = m - k0 - 1;
       const int nh1 = nbt < kNBh ? nbt : kNBh, nh2 = nbt - nh1;
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
-      // G = V^T V, lower tiles only (G is symmetric)
-      wg_gemm<T, kBackNW, true, false, true, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
+      // G = V^T V, lower tiles only (G is symmetric); V's zeros above each
+      // vector's first entry are skipped
+      wg_gemm<T, kBackNW, true, false, true, 1, 2, 2, 1, 1>(nbt, nbt, n2, T(1), V, ld, V, ld, T(0), Gm, kNBq, gsm);
       for (int q = tid; q < kNBq * kNBq; q += kBackBlock) Tm[q] = T(0);
       __syncthreads();
       wy_factor_half<T>(Gm, Tm, tau + k0, 0, nh1, Ts);
@@ -1389,9 +1390,10 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_prep(LargeArgs 
         wg_gemm<T, kBackNW, false, false, false, 1>(nh1, nh2, nh1, T(-1), Tm, kNBq, Xm, kNBh, T(0),
                                                    Tm + (int64_t)kNBh * kNBq, kNBq, gsm);
       }
-      // VT = V T^T (n2 x nbt) over V's position in the W slab
-      wg_gemm<T, kBackNW, false, true, false, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0),
-                                                VTs + (int64_t)k0 * ld + (k0 + 1), ld, gsm);
+      // VT = V T^T (n2 x nbt) over V's position in the W slab: V(r, k) = 0
+      // for r < k and T(j, k) = 0 for k < j, so VT(r, j) = 0 for r < j
+      wg_gemm<T, kBackNW, false, true, false, 1, 2, 2, 2, 1>(n2, nbt, nbt, T(1), V, ld, Tm, kNBq, T(0),
+                                                            VTs + (int64_t)k0 * ld + (k0 + 1), ld, gsm);
     }
   }
 }
@@ -1432,9 +1434,10 @@ __global__ __launch_bounds__(kBackBlock, kBackPerCU) void k_back_apply(LargeArgs
       const T* V = S + (int64_t)k0 * ld + (k0 + 1);
       const T* VT = VTs + (int64_t)k0 * ld + (k0 + 1);
       T* Qs = Q + (k0 + 1);
-      // Wm = VT^T Q_sub (nbt x nc; one 128 x 64 tile, so Q_sub is read once), Q_sub -= V Wm
-      wg_gemm<T, kBackNW, true, false, false, 1, 4, 2>(nbt, nc, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
-      wg_gemm<T, kBackNW, false, false, false, 1>(n2, nc, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
+      // Wm = VT^T Q_sub (nbt x nc; one 128 x 64 tile, so Q_sub is read once), Q_sub -= V Wm;
+      // the zeros of VT(r, j) (r < j) and V(r, k) (r < k) are skipped
+      wg_gemm<T, kBackNW, true, false, false, 1, 4, 2, 1, 0>(nbt, nc, n2, T(1), VT, ld, Qs, ld, T(0), Wm, kNBq, gsm);
+      wg_gemm<T, kBackNW, false, false, false, 1, 2, 2, 2, 0>(n2, nc, nbt, T(-1), V, ld, Wm, kNBq, T(1), Qs, ld, gsm);
     }
   }
 }

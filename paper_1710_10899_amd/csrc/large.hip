@@ -136,7 +136,9 @@ constexpr int kStrip = 8;
 // row groups of 64 per strip iteration of the symv, by element type (two for
 // both: four groups of 4-byte elements raised the FP32 reduction's register
 // use past what three workgroups per compute unit allow, and were slower,
-// 141.9 against 137.0 ms on the 6656-column workload)
+// 141.9 against 137.0 ms on the 6656-column workload; three groups of 8-byte
+// elements fit two FP64 workgroups per compute unit without spills but took
+// 156.0 against 150.5 ms)
 template <class T> constexpr int kSymvGroups = 2;
 template <> constexpr int kSymvGroups<float> = 2;
 

@@ -181,6 +181,8 @@ def summarise_profile(d: str, command: str, workload: int, precision: str) -> No
     and the matching traffic_*.json. The 1 GiB probe copy calibrates the
     byte counters: scale = bytes moved / bytes the counter reports for it."""
     import csv
+
+    from workloads import generators as G
     stats = {}
     with open(os.path.join(d, "kt_kernel_stats.csv")) as fh:
         for r in csv.DictReader(fh):
@@ -211,7 +213,9 @@ def summarise_profile(d: str, command: str, workload: int, precision: str) -> No
     sha = kernel_source_hash()
     tag = WORKLOAD_TAGS[workload]
     phases = {}
-    lines = [f"# rocprofv3 summary: submatrix-method kernels, {tag} ({WORKLOAD_NAMES[workload].split(';')[0]}), "
+    # the profiled commands take the workload's default condition number and p = 2
+    name = WORKLOAD_NAMES[workload].format(kappa=G.DEFAULT_KAPPA.get(workload, 0.0), p=2).split(";")[0]
+    lines = [f"# rocprofv3 summary: submatrix-method kernels, {tag} ({name}), "
              f"forward + adjoint, {precision}", "", "Commands (from the repository root, `cd /tmp && export "
              "TMPDIR=/tmp` first; the output directory is then passed to `python bench.py --summarise-profile DIR "
              f"--workload {workload} --precision {precision}`):", "", "```", command, "```", "",

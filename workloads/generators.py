@@ -363,20 +363,25 @@ UNSHIFTED_EXTREMES = {
 }
 
 
+# condition number of each named workload when none is given (the banded
+# workload is diagonally dominant and not shifted)
+DEFAULT_KAPPA = {2: 1e2, 3: 1e2, 4: 1e2, 5: 1e6}
+
+
 def make_config(idx: int, kappa: float | None = None, unshifted: bool = False) -> CSR:
     seed = BASE_SEED + idx
     if idx == 1:
         return banded_spd(1024, 8, seed=seed)
     if idx == 2:
-        return overlap_matrix(512, 0.1, 13, 4.14, None if unshifted else (kappa or 1e2), seed=seed)
+        return overlap_matrix(512, 0.1, 13, 4.14, None if unshifted else (kappa or DEFAULT_KAPPA[2]), seed=seed)
     if idx == 4:
-        return overlap_matrix(1024, 0.1, 13, 4.14, None if unshifted else (kappa or 1e2), seed=seed)
+        return overlap_matrix(1024, 0.1, 13, 4.14, None if unshifted else (kappa or DEFAULT_KAPPA[4]), seed=seed)
     if idx == 3:
         csr = mixed_density_overlap(4096, kappa=None, seed=seed)
-        k = kappa or 1e2
+        k = kappa or DEFAULT_KAPPA[3]
     elif idx == 5:
         csr = overlap_matrix(16384, 0.1, 13, 4.47, None, seed=seed)
-        k = kappa or 1e6
+        k = kappa or DEFAULT_KAPPA[5]
     else:
         raise ValueError(f"unknown workload {idx}")
     return csr if unshifted else shift_to_kappa(csr, k, UNSHIFTED_EXTREMES.get(idx))

@@ -61,6 +61,17 @@ def test_dense_with_spectrum_has_that_spectrum():
     assert c.nnz == 144
 
 
+def test_lanczos_shift_is_reproducible():
+    """Above the dense-eigensolver size the extremes come from Lanczos with a
+    seeded start vector, so generating a workload twice gives the same bits
+    (the shift lands on every diagonal entry)."""
+    a = G.make_config(2)
+    b = G.make_config(2)
+    assert a.n > 3000
+    assert np.array_equal(a.vals, b.vals) and a.meta["sigma"] == b.meta["sigma"]
+    assert abs(a.meta["lmax"] / a.meta["lmin"] - 1e2) <= 1e-8 * 1e2
+
+
 def test_cached_extremes_match_lanczos_on_a_smaller_matrix():
     """The cached-extremes path of shift_to_kappa places the same shift as
     computing the extremes (checked where Lanczos is cheap)."""

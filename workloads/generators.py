@@ -75,9 +75,13 @@ def extreme_eigenvalues(csr: CSR) -> tuple[float, float]:
         return float(w[0]), float(w[-1])
     from scipy.sparse.linalg import eigsh
     a = csr.to_scipy()
-    lmax = eigsh(a, k=1, which="LA", tol=1e-13, return_eigenvectors=False, ncv=48)[0]
+    # a seeded start vector: without one ARPACK draws its own, differently on
+    # every call, and the extremes (hence the shift and every diagonal entry)
+    # moved in their last bits from one generation of a workload to the next
+    v0 = np.random.default_rng(BASE_SEED).standard_normal(csr.n)
+    lmax = eigsh(a, k=1, which="LA", tol=1e-13, return_eigenvectors=False, ncv=48, v0=v0)[0]
     lmin = eigsh(a, k=1, which="SA", tol=1e-13, return_eigenvectors=False, ncv=64,
-                 maxiter=100000)[0]
+                 maxiter=100000, v0=v0)[0]
     return float(lmin), float(lmax)
 
 
